@@ -1,0 +1,313 @@
+"""CPU oracle for local adaptive binarization statistics.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the product path.  It shares no
+code with the HIP library under ``paper_1905_13038_amd``.
+
+``oracle.c`` (plain C, binary64, built with ``-ffp-contract=off``) holds the
+definitions; this module loads it with ctypes and adds NumPy conveniences.
+``brute.py`` holds pure-Python forms for tiny inputs and exact rational
+decisions.  Function docstrings cite the paper passage each one follows.
+
+Parity status: every function here is pinned by the ``-m "not gpu"`` tests
+(brute force, integral images, closed forms, invariants, library order
+statistics, finite differences); none is "parity unpinned" except the choice
+of quantile definition itself (the paper does not define one; the inverse
+empirical CDF is used).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MEANSTD, SAUVOLA, NIBLACK = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (no fast-math, no
+    contraction: every binary64 operation rounds once)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i32, i64, f32, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    lib.orc_count.restype = i64
+    lib.orc_count.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.orc_sums_direct.restype = None
+    lib.orc_sums_direct.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.orc_sums_direct_at.restype = None
+    lib.orc_sums_direct_at.argtypes = [P, i32, i32, i64, i32, i32, i32, P, P, P, P]
+    lib.orc_sums_recursive.restype = i32
+    lib.orc_sums_recursive.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.orc_sums_integral.restype = i32
+    lib.orc_sums_integral.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.orc_threshold.restype = None
+    lib.orc_threshold.argtypes = [P, i32, i32, i64, i32, i32, P, P, i32, f32, f32, P, P, P, P]
+    lib.orc_sauvola_sqrtfree.restype = None
+    lib.orc_sauvola_sqrtfree.argtypes = [P, i32, i32, i64, i32, i32, P, P, f32, f32, P]
+    lib.orc_rank.restype = i64
+    lib.orc_rank.argtypes = [f64, i64]
+    lib.orc_quantile_sort.restype = None
+    lib.orc_quantile_sort.argtypes = [P, i32, i32, i64, i32, i32, f64, P, P]
+    lib.orc_quantile_hist.restype = None
+    lib.orc_quantile_hist.argtypes = [P, i32, i32, i64, i32, i32, f64, P, P]
+    lib.orc_soft_fwd.restype = None
+    lib.orc_soft_fwd.argtypes = [P, i32, i32, i32, i32, i32, P, f64, f64, P, P]
+    lib.orc_box_f64.restype = None
+    lib.orc_box_f64.argtypes = [P, i32, i32, i32, i32, P]
+    lib.orc_box_adjoint.restype = None
+    lib.orc_box_adjoint.argtypes = [P, i32, i32, i32, i32, P]
+    lib.orc_soft_bwd.restype = None
+    lib.orc_soft_bwd.argtypes = [P, P, i32, i32, i32, i32, i32, P, f64, f64, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _img(I: np.ndarray):
+    """Return (array, H, W, ld) for a 2-D uint8 view with unit column stride."""
+    I = np.asarray(I)
+    if I.dtype != np.uint8 or I.ndim != 2:
+        raise TypeError("expected a 2-D uint8 image")
+    if I.strides[1] != 1:
+        I = np.ascontiguousarray(I)
+    H, W = I.shape
+    ld = I.strides[0] if H > 1 else W
+    return I, H, W, ld
+
+
+def extents(h: int, w: int):
+    """(o, u, l, r) of Algorithm 1."""
+    return (h + 1) // 2, h // 2, (w + 1) // 2, w // 2
+
+
+def count(H: int, W: int, h: int, w: int, i: int, j: int) -> int:
+    """In-bounds window count n of Algorithm 1."""
+    return int(_load().orc_count(H, W, h, w, i, j))
+
+
+def count_map(H: int, W: int, h: int, w: int) -> np.ndarray:
+    """n for every pixel (int64, H x W): the product of Algorithm 1's row and
+    column factors."""
+    o, u, l, r = extents(h, w)
+    i = np.arange(H)
+    j = np.arange(W)
+    nr = np.minimum(i + u, H - 1) - np.maximum(i - o, -1)
+    nc = np.minimum(j + r, W - 1) - np.maximum(j - l, -1)
+    return nr[:, None].astype(np.int64) * nc[None, :].astype(np.int64)
+
+
+def sums_direct(I, h: int, w: int):
+    """S1, S2 (uint64) by the direct definition of the Introduction."""
+    I, H, W, ld = _img(I)
+    S1 = np.empty((H, W), np.uint64)
+    S2 = np.empty((H, W), np.uint64)
+    _load().orc_sums_direct(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2))
+    return S1, S2
+
+
+def sums_direct_at(I, h: int, w: int, ii, jj):
+    """S1, S2 at the listed pixels only (direct definition)."""
+    I, H, W, ld = _img(I)
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    S1 = np.empty(ii.size, np.uint64)
+    S2 = np.empty(ii.size, np.uint64)
+    _load().orc_sums_direct_at(_ptr(I), H, W, ld, h, w, ii.size, _ptr(ii), _ptr(jj),
+                               _ptr(S1), _ptr(S2))
+    return S1, S2
+
+
+def sums_recursive(I, h: int, w: int):
+    """S1, S2 (uint32) by Algorithm 1's recursive sweep (16/32-bit
+    accumulators of Section 3.3)."""
+    I, H, W, ld = _img(I)
+    S1 = np.empty((H, W), np.uint32)
+    S2 = np.empty((H, W), np.uint32)
+    rc = _load().orc_sums_recursive(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2))
+    if rc != 0:
+        raise ValueError("recursive sums need h, w <= 257")
+    return S1, S2
+
+
+def sums_integral(I, h: int, w: int):
+    """S1, S2 (uint64) from two 64-bit integral images (Section 2)."""
+    I, H, W, ld = _img(I)
+    S1 = np.empty((H, W), np.uint64)
+    S2 = np.empty((H, W), np.uint64)
+    rc = _load().orc_sums_integral(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2))
+    if rc != 0:
+        raise MemoryError("integral image allocation failed")
+    return S1, S2
+
+
+def threshold(I, h: int, w: int, method: int, k: float = 0.0, R: float = 128.0,
+              S1=None, S2=None):
+    """Canonical binary64 moments, threshold and mask (mask = 1 iff I < t).
+
+    Returns dict(m, s, t, mask, S1, S2).  ``k`` and ``R`` are rounded to
+    float32 first, as the C-ABI takes them."""
+    I, H, W, ld = _img(I)
+    if S1 is None:
+        S1, S2 = sums_recursive(I, h, w) if max(h, w) <= 257 else sums_integral(I, h, w)
+    S1 = np.ascontiguousarray(S1, dtype=np.uint64)
+    S2 = np.ascontiguousarray(S2, dtype=np.uint64)
+    m = np.empty((H, W), np.float64)
+    s = np.empty((H, W), np.float64)
+    t = np.empty((H, W), np.float64)
+    mask = np.empty((H, W), np.uint8)
+    _load().orc_threshold(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2), method,
+                          float(np.float32(k)), float(np.float32(R)),
+                          _ptr(m), _ptr(s), _ptr(t), _ptr(mask))
+    return dict(m=m, s=s, t=t, mask=mask, S1=S1, S2=S2)
+
+
+def sauvola(I, h, w, k=0.5, R=128.0, **kw):
+    """Sauvola (Introduction; Table 1) in the canonical binary64 sequence."""
+    return threshold(I, h, w, SAUVOLA, k, R, **kw)
+
+
+def niblack(I, h, w, k=-0.2, **kw):
+    """Niblack (Table 1) in the canonical binary64 sequence."""
+    return threshold(I, h, w, NIBLACK, k, 128.0, **kw)
+
+
+def sauvola_sqrtfree(I, h: int, w: int, k: float, R: float, S1=None, S2=None):
+    """Section 3.2's square-root-free decision; returns the paper's output bit
+    (1 = background, i.e. I > t away from ties)."""
+    I, H, W, ld = _img(I)
+    if S1 is None:
+        S1, S2 = sums_integral(I, h, w)
+    S1 = np.ascontiguousarray(S1, dtype=np.uint64)
+    S2 = np.ascontiguousarray(S2, dtype=np.uint64)
+    out = np.empty((H, W), np.uint8)
+    _load().orc_sauvola_sqrtfree(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2),
+                                 float(np.float32(k)), float(np.float32(R)), _ptr(out))
+    return out
+
+
+def rank(q: float, n: int) -> int:
+    """rho = max(1, ceil(q * n)) with q * n in binary64."""
+    return int(_load().orc_rank(float(q), int(n)))
+
+
+def quantile_sort(I, h: int, w: int, q: float):
+    """Windowed quantile by sorting each clipped window (the definition)."""
+    I, H, W, ld = _img(I)
+    Q = np.empty((H, W), np.uint8)
+    mask = np.empty((H, W), np.uint8)
+    _load().orc_quantile_sort(_ptr(I), H, W, ld, h, w, float(q), _ptr(Q), _ptr(mask))
+    return Q, mask
+
+
+def quantile_hist(I, h: int, w: int, q: float):
+    """Windowed quantile by sliding 256-bin histograms (Section 3.4)."""
+    I, H, W, ld = _img(I)
+    Q = np.empty((H, W), np.uint8)
+    mask = np.empty((H, W), np.uint8)
+    _load().orc_quantile_hist(_ptr(I), H, W, ld, h, w, float(q), _ptr(Q), _ptr(mask))
+    return Q, mask
+
+
+def box_f64(x, h: int, w: int):
+    """Window sum B x of a binary64 field over each clipped window (direct)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    H, W = x.shape
+    out = np.empty((H, W), np.float64)
+    _load().orc_box_f64(_ptr(x), H, W, h, w, _ptr(out))
+    return out
+
+
+def box_adjoint(G, h: int, w: int):
+    """Adjoint B* G of the window sum: the sum of G over the centres whose
+    window contains each pixel (the reflected, clipped window)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    H, W = G.shape
+    out = np.empty((H, W), np.float64)
+    _load().orc_box_adjoint(_ptr(G), H, W, h, w, _ptr(out))
+    return out
+
+
+def soft_fwd(I, h: int, w: int, k, R: float, tau: float):
+    """Soft Sauvola forward in binary64: y = sigmoid((I - t) / tau) for a
+    (B, H, W) float32 stack; returns (y, t)."""
+    I = np.ascontiguousarray(I, dtype=np.float32)
+    if I.ndim == 2:
+        I = I[None]
+    B, H, W = I.shape
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.float64), (B,)))
+    y = np.empty((B, H, W), np.float64)
+    t = np.empty((B, H, W), np.float64)
+    _load().orc_soft_fwd(_ptr(I), B, H, W, h, w, _ptr(k), float(R), float(tau), _ptr(y), _ptr(t))
+    return y, t
+
+
+def soft_bwd(I, g, h: int, w: int, k, R: float, tau: float):
+    """Gradients of sum(g * y) w.r.t. I, k (per image) and R, binary64."""
+    I = np.ascontiguousarray(I, dtype=np.float32)
+    if I.ndim == 2:
+        I = I[None]
+    B, H, W = I.shape
+    g = np.ascontiguousarray(np.broadcast_to(np.asarray(g, np.float64), (B, H, W)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.float64), (B,)))
+    gI = np.empty((B, H, W), np.float64)
+    gk = np.empty(B, np.float64)
+    gR = np.empty(1, np.float64)
+    _load().orc_soft_bwd(_ptr(I), _ptr(g), B, H, W, h, w, _ptr(k), float(R), float(tau),
+                         _ptr(gI), _ptr(gk), _ptr(gR))
+    return gI, gk, float(gR[0])
+
+
+def time_recursive_sauvola(I, h: int, w: int, k: float, R: float, min_seconds: float = 10.0):
+    """Wall-clock Mpix/s of the oracle's Algorithm 1 sweep plus the canonical
+    threshold on one thread (repeated until ``min_seconds`` have passed).
+    Returns (mpix_per_s, repeats, seconds)."""
+    I, H, W, ld = _img(I)
+    lib = _load()
+    S1 = np.empty((H, W), np.uint32)
+    S2 = np.empty((H, W), np.uint32)
+    S1w = np.empty((H, W), np.uint64)
+    S2w = np.empty((H, W), np.uint64)
+    m = np.empty((H, W), np.float64)
+    s = np.empty((H, W), np.float64)
+    mask = np.empty((H, W), np.uint8)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        lib.orc_sums_recursive(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2))
+        np.copyto(S1w, S1)
+        np.copyto(S2w, S2)
+        lib.orc_threshold(_ptr(I), H, W, ld, h, w, _ptr(S1w), _ptr(S2w), SAUVOLA,
+                          float(np.float32(k)), float(np.float32(R)), _ptr(m), _ptr(s),
+                          None, _ptr(mask))
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return reps * H * W / dt / 1e6, reps, dt
