@@ -1,0 +1,183 @@
+"""Benchmark of the Sauvola hot path on one MI355X.
+
+Default workload: Sauvola on a 4096 x 3072 (W x H) uint8 synthetic document,
+h = w = 75, k = 0.5, R = 128, writing the uint8 mask plus float32 window mean
+and standard deviation (10 bytes of algorithmic HBM traffic per pixel).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras] [--pmc]
+
+Prints ONE JSON line.  `value` is Gpix/s over the K timed steps (inputs
+resident in HBM; buffer sets rotated so the 256 MB Infinity Cache cannot serve
+repeats).  `roofline` prices the kernel's average duration (HIP events around
+each launch, on the stream the kernel runs on) against the 8 TB/s HBM peak.
+`cpu_baseline` times the CPU oracle (Algorithm 1 sweep plus the binary64
+threshold, one thread) on the same page.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "Gpix/s Sauvola 4096×3072 w=75 (% HBM peak); batched & fwd+bwd vs plain"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_sauvola_4096x3072_w75.txt")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("box.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1905_13038_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(launch_px: int):
+    """Counter-derived HBM bytes per launch from the committed profile
+    summary, or None if it is missing or was taken on other kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    vals = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(I, h, w, k, R, seconds):
+    import oracle
+    mpix, reps, dt = oracle.time_recursive_sauvola(I, h, w, k, R, min_seconds=seconds)
+    return {
+        "value": round(mpix / 1000.0, 6),
+        "unit": "Gpix/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "%d full passes of the %dx%d page (Algorithm 1 sweep + binary64 threshold, "
+                  "one thread, %.1f s, %s)" % (reps, I.shape[1], I.shape[0], dt,
+                                               platform.processor() or platform.machine()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sets", type=int, default=8, help="rotated buffer sets")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--pmc", action="store_true",
+                    help="counter run: 3 launches + 3 plain 128 MiB copies, no JSON")
+    ap.add_argument("--win", type=int, default=75)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1905_13038_amd as bz
+    from docgen import gen_document
+
+    H, W, win, k, R = 3072, 4096, args.win, 0.5, 128.0
+    host = gen_document(H, W, 2, noise=10.0, stain=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sets = []
+    for s in range(args.sets):
+        img = torch.from_numpy(host).to(dev) if s == 0 else sets[0][0].clone()
+        mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        m = torch.empty((H, W), dtype=torch.float32, device=dev)
+        sd = torch.empty((H, W), dtype=torch.float32, device=dev)
+        sets.append((img, mask, m, sd))
+    torch.cuda.synchronize()
+
+    def step(i):
+        img, mask, m, sd = sets[i % len(sets)]
+        bz.sauvola(img, win, win, k=k, R=R, mask=mask, mean=m, std=sd)
+
+    if args.pmc:
+        for i in range(3):
+            step(i)
+        src = torch.empty(128 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("pmc workload done", flush=True)
+        return
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    # whole-job timing of K steps
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    # per-launch kernel duration: an event pair around each launch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for i, (a, b) in enumerate(evs):
+        a.record(stream)
+        step(i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+
+    px = H * W
+    ms_per_step = total_ms / args.steps
+    value = px / (ms_per_step * 1e-3) / 1e9
+    alg_bytes = 10.0 * px
+    launch_ms = float(per.mean())
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = read_traffic(px)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32+f32",
+        "data": "synthetic",
+        "config": {"workload": "sauvola_4096x3072_w%d" % win, "W": W, "H": H, "h": win, "w": win,
+                   "k": k, "R": R, "outputs": "mask u8 + mean f32 + std f32",
+                   "buffer_sets": args.sets},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_box<MODE_SAUVOLA>",
+                     "launch_us_mean": round(launch_ms * 1e3, 3),
+                     "launch_us_median": round(float(np.median(per)) * 1e3, 3)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(host, win, win, k, R, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

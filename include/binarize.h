@@ -1,0 +1,177 @@
+/*
+ * binarize.h -- C ABI of the MI355X (gfx950) library for the sliding-window
+ * statistics of local adaptive binarization (Chan, "Memory-efficient and fast
+ * implementation of local adaptive binarization methods").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Images.  Row-major, element (i, j) at base[i * ld + j], 0 <= i < H rows,
+ *   0 <= j < W columns; every `ld_*` is a row stride in ELEMENTS and must be
+ *   >= W.  Gray levels are uint8 (0..255).
+ * Window.  h rows by w columns.  With o = floor((h+1)/2), u = floor(h/2),
+ *   l = floor((w+1)/2), r = floor(w/2) (Algorithm 1), the window of pixel
+ *   (i, j) is rows i-o+1 .. i+u and columns j-l+1 .. j+r, i.e. the bounds
+ *   i - h/2 < a <= i + h/2 of the Introduction's mean formula.  Windows are
+ *   clipped to the image: out-of-image pixels are zero (Section 3.2) and the
+ *   divisor is the in-bounds count n of Algorithm 1.  1 <= h, w <= 257: within
+ *   that range the column sums fit 16 bits and the window sum of squares fits
+ *   32 bits (Section 3.3).
+ * Memory.  Every pointer is DEVICE memory owned by the caller unless stated
+ *   otherwise.  The library never allocates, frees or synchronises; a call
+ *   enqueues its kernels on `stream` and returns.  Outputs must not overlap
+ *   the input (Section 3.2's aliasing assumption); overlapping byte ranges are
+ *   rejected with BZ_ERR_ALIAS.  32-bit outputs must be 4-byte aligned.
+ * Stream.  `stream` is a hipStream_t (NULL = the null stream).
+ * Errors.  Arguments are validated before any HIP call; an invalid call
+ *   returns its status and enqueues nothing.  BZ_ERR_HIP reports a launch
+ *   failure.  Output contents are undefined after an error.  Calls are
+ *   re-entrant; calls on different streams may run concurrently.
+ */
+#ifndef BINARIZE_H
+#define BINARIZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *bz_stream; /* hipStream_t */
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_ERR_INVALID = 1,   /* bad size, stride, pointer or parameter */
+    BZ_ERR_RANGE = 2,     /* h or w above 257, or sizes beyond 2^31 */
+    BZ_ERR_ALIAS = 3,     /* an output overlaps the input */
+    BZ_ERR_WORKSPACE = 4, /* caller workspace too small */
+    BZ_ERR_HIP = 5        /* the HIP runtime reported an error */
+} bz_status;
+
+/* Human-readable name of a status code (static string). */
+const char *bz_status_string(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int bz_version(void);
+
+/* Largest accepted window side (257, Section 3.3). */
+int bz_max_window(void);
+
+/*
+ * Window sums S1 = sum I and S2 = sum I^2 over each pixel's clipped window
+ * (the quantity Algorithm 1 maintains in c and d; the Introduction's
+ * definition).  S1, S2: uint32 H x W with row stride ld_S; both exact.
+ */
+bz_status bz_window_sums(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
+                         uint32_t *S1, uint32_t *S2, ptrdiff_t ld_S, bz_stream stream);
+
+/*
+ * Window mean m = S1/n and population standard deviation
+ * s = sqrt(n S2 - S1^2) / n (Introduction, with Algorithm 1's divisor n).
+ * n S2 - S1^2 is formed exactly in 64-bit integer arithmetic; m and s are
+ * float32, within 1e-6 relative of the binary64 values, and s == 0 exactly
+ * where the window is constant.  mean, std: float H x W, row stride ld_out.
+ */
+bz_status bz_window_mean_std(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
+                             float *mean, float *std, ptrdiff_t ld_out, bz_stream stream);
+
+/*
+ * Sauvola binarization (Introduction; Table 1): t = m (1 + k (s/R - 1)) and
+ * mask = 1 where I < t, else 0.  k >= 0 (Algorithm 1's input), R > 0.
+ * mask: uint8 H x W, row stride ld_mask.  mean, std: optional float32 outputs
+ * (NULL to skip), row stride ld_ms.  The mask equals that of the binary64
+ * sequence m = S1/n, v = (n S2 - S1^2)/(n n), s = sqrt(v),
+ * t = m * (1 + k * (s/R - 1)), each operation rounded once, with k and R
+ * widened from float.
+ */
+bz_status bz_sauvola(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, float k,
+                     float R, uint8_t *mask, ptrdiff_t ld_mask, float *mean, float *std,
+                     ptrdiff_t ld_ms, bz_stream stream);
+
+/*
+ * Niblack binarization (Table 1): t = m + k s, any finite k; mask = 1 where
+ * I < t.  Outputs as bz_sauvola; the binary64 sequence is t = m + k * s.
+ */
+bz_status bz_niblack(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, float k,
+                     uint8_t *mask, ptrdiff_t ld_mask, float *mean, float *std,
+                     ptrdiff_t ld_ms, bz_stream stream);
+
+/*
+ * Windowed quantile from sliding 256-bin gray-level histograms (Section 3.4):
+ * Q = the rho-th smallest gray level of the clipped window, with
+ * rho = max(1, ceil(q * n)) evaluated in binary64 (0 <= q <= 1; q = 0.5 is
+ * the lower median, q = 1 the maximum).  Q: uint8 H x W (row stride ld_Q);
+ * mask (optional, NULL to skip): 1 where I < Q, row stride ld_mask.
+ */
+bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
+                             double q, uint8_t *Q, ptrdiff_t ld_Q, uint8_t *mask,
+                             ptrdiff_t ld_mask, bz_stream stream);
+
+/* Thresholding rule of a batched item. */
+enum { BZ_METHOD_SAUVOLA = 1, BZ_METHOD_NIBLACK = 2 };
+
+/* One image of a ragged batch; pointers are device memory, mean/std may be
+ * NULL.  Each item has its own size, strides, window and parameters. */
+typedef struct {
+    const uint8_t *I;
+    uint8_t *mask;
+    float *mean;
+    float *std;
+    int H, W, h, w;
+    ptrdiff_t ld_I, ld_mask, ld_ms;
+    float k, R;
+    int method; /* BZ_METHOD_SAUVOLA or BZ_METHOD_NIBLACK */
+} bz_item;
+
+/* Workspace bytes that bz_sauvola_batched needs for `count` items. */
+size_t bz_batched_workspace_size(int count);
+
+/*
+ * Binarize a ragged batch in ONE persistent kernel launch.  `items` is a HOST
+ * array of `count` descriptors; it is read during the call (its contents are
+ * uploaded into `workspace`, device memory of at least
+ * bz_batched_workspace_size(count) bytes, by an asynchronous copy on
+ * `stream`).  Each item's outputs equal those of bz_sauvola / bz_niblack on
+ * that item alone.  The host array may be reused as soon as the call returns
+ * only if `stream` is synchronised first (the copy is asynchronous); the
+ * workspace must stay untouched until the launch completes.  Items must not
+ * alias each other's outputs.
+ */
+bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace,
+                             size_t ws_bytes, bz_stream stream);
+
+/* Workspace bytes of the soft-Sauvola backward for B images of H x W. */
+size_t bz_soft_workspace_size(int B, int H, int W);
+
+/*
+ * Differentiable ("soft") Sauvola forward: for B float32 images of H x W
+ * (values nominally in [0, 255]; image b at I + b * H * ld, row stride ld),
+ * window sums in binary64, m, s and t = m (1 + k_b (s/R - 1)) as above, and
+ * y = 1 / (1 + exp(-(I - t) / tau)).  k: float[B] on the device, R: float[1]
+ * on the device, tau > 0.  y: float32 with the same layout as I.
+ */
+bz_status bz_soft_sauvola_fwd(const float *I, int B, int H, int W, ptrdiff_t ld, int h, int w,
+                              const float *k, const float *R, float tau, float *y,
+                              bz_stream stream);
+
+/*
+ * Backward of bz_soft_sauvola_fwd for an upstream gradient gy = dL/dy (same
+ * layout as I).  Recomputes the window statistics from I (nothing is saved
+ * by the forward); the gradient reaching I through the window sums is the
+ * adjoint window sum: pixel q collects from the centres p whose window holds
+ * q (rows q-u .. q+o-1, columns q-r .. q+l-1, clipped).  Where s = 0 the
+ * derivative of s does not exist and its terms are dropped.  Writes
+ * gI (layout of I), gk (float[B]) and gR (float[1]); reductions are
+ * deterministic (fixed order).  workspace: device memory of at least
+ * bz_soft_workspace_size(B, H, W) bytes.
+ */
+bz_status bz_soft_sauvola_bwd(const float *I, const float *gy, int B, int H, int W, ptrdiff_t ld,
+                              int h, int w, const float *k, const float *R, float tau,
+                              float *gI, float *gk, float *gR, void *workspace, size_t ws_bytes,
+                              bz_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BINARIZE_H */

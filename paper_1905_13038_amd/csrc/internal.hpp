@@ -1,0 +1,74 @@
+// Internal declarations shared by the HIP translation units of libbinarize.
+// Not part of the public C ABI (include/binarize.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bz {
+
+// What the box-statistics kernel writes.
+enum Mode : int {
+    MODE_SUMS = 0,     // S1, S2 (uint32)
+    MODE_MEANSTD = 1,  // m, s (float)
+    MODE_SAUVOLA = 2,  // mask (+ optional m, s)
+    MODE_NIBLACK = 3   // mask (+ optional m, s)
+};
+
+// Columns owned by one lane in the box kernels (one dword of pixels).
+constexpr int COLS_PER_LANE = 4;
+// Largest block: 16 waves of 64 lanes.
+constexpr int MAX_THREADS = 1024;
+constexpr int MAX_WAVES = MAX_THREADS / 64;
+
+// Per-image description of one box-statistics job, with its tiling.
+struct BoxJob {
+    const uint8_t *I;
+    int64_t ldI;
+    int H, W, h, w;
+    int o, u, l, r;        // window extents (Algorithm 1)
+    // outputs (unused ones are null)
+    uint32_t *S1, *S2;
+    int64_t ldS;
+    float *mean, *stdv;
+    int64_t ldMS;
+    uint8_t *mask;
+    int64_t ldM;
+    // threshold parameters: float fast path and binary64 canonical path
+    float c0, c1;          // Sauvola: 1 - k, k / R; Niblack: unused, c1 = k
+    float kabs;            // |k| (Niblack guard)
+    double k64, R64;
+    float rh;              // 1 / h, rounded (interior-row reciprocal)
+    int mode;
+    // tiling: column tiles of tile_w outputs, row strips of `strip` rows
+    int threads;           // block size (multiple of 64, <= 1024)
+    int tile_w, ntx, halo_l;
+    int strip, nsy;
+    int aligned;           // all pointers/strides allow vector access
+    int force_ref;         // decide every pixel with the binary64 sequence (testing)
+};
+
+// Fill o,u,l,r and the tiling of `job` (threads, tile_w, ntx, halo_l, strip,
+// nsy) for a stand-alone launch.  `strip_override` > 0 forces the strip
+// height; `threads_override` > 0 forces the block size.
+void plan_box(BoxJob &job, int strip_override, int threads_override);
+
+// Enqueue the box-statistics kernel for one planned job.
+hipError_t launch_box(const BoxJob &job, hipStream_t stream);
+
+// Windowed quantile (Section 3.4).
+struct QuantJob {
+    const uint8_t *I;
+    int64_t ldI;
+    int H, W, h, w;
+    int o, u, l, r;
+    double q;
+    uint8_t *Q;
+    int64_t ldQ;
+    uint8_t *mask;
+    int64_t ldM;
+};
+hipError_t launch_quantile(const QuantJob &job, hipStream_t stream);
+
+}  // namespace bz
