@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     ap.add_argument("--pmc", action="store_true",
-                    help="counter run: 3 launches + 3 plain 128 MiB copies, no JSON")
+                    help="counter run: 3 launches + 3 plain 1 GiB copies, no JSON")
     ap.add_argument("--win", type=int, default=75)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -113,7 +113,7 @@ def main():
     if args.pmc:
         for i in range(3):
             step(i)
-        src = torch.empty(128 << 20, dtype=torch.uint8, device=dev)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)

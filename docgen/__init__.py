@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["gen_document", "batch_specs", "soft_batch", "INK_TARGET"]
+__all__ = ["gen_document", "gen_batch", "batch_specs", "soft_batch", "INK_TARGET"]
 
 INK_TARGET = 0.10
 
@@ -167,3 +167,20 @@ def soft_batch(B: int = 32, H: int = 1024, W: int = 1024):
     k = np.random.default_rng(5998).uniform(0.2, 0.5, size=B).astype(np.float32)
     wr = np.random.default_rng(5999).standard_normal((B, H, W), dtype=np.float32)
     return imgs, k, wr
+
+
+def _gen_one(args):
+    H, W, seed, noise, stain = args
+    return gen_document(H, W, seed, noise=noise, stain=stain)
+
+
+def gen_batch(specs, noise: float = 10.0, stain: bool = True, workers: int = 8):
+    """uint8 pages for a list of specs (dicts with H, W, seed), generated in
+    fresh worker processes (spawned interpreters) when workers > 1."""
+    jobs = [(d["H"], d["W"], d["seed"], noise, stain) for d in specs]
+    if workers <= 1 or len(jobs) < 4:
+        return [_gen_one(j) for j in jobs]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_gen_one, jobs, chunksize=4))

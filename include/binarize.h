@@ -127,18 +127,34 @@ typedef struct {
 size_t bz_batched_workspace_size(int count);
 
 /*
- * Binarize a ragged batch in ONE persistent kernel launch.  `items` is a HOST
- * array of `count` descriptors; it is read during the call (its contents are
- * uploaded into `workspace`, device memory of at least
- * bz_batched_workspace_size(count) bytes, by an asynchronous copy on
- * `stream`).  Each item's outputs equal those of bz_sauvola / bz_niblack on
- * that item alone.  The host array may be reused as soon as the call returns
- * only if `stream` is synchronised first (the copy is asynchronous); the
- * workspace must stay untouched until the launch completes.  Items must not
- * alias each other's outputs.
+ * Binarize a ragged batch in ONE persistent kernel launch (bz_batched_plan
+ * followed by bz_batched_run).  `items` is a HOST array of `count`
+ * descriptors, read during the call; `workspace` is device memory of at least
+ * bz_batched_workspace_size(count) bytes, 64-byte aligned, that must stay
+ * untouched until the launch completes.  Each item's outputs equal those of
+ * bz_sauvola / bz_niblack on that item alone.  Items must not alias each
+ * other's outputs (not checked).  Synchronises `stream` once, after the
+ * descriptor upload and before the launch.
  */
 bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace,
                              size_t ws_bytes, bz_stream stream);
+
+/*
+ * Two-step form of bz_sauvola_batched for callers that replay the same batch
+ * (for example inside a captured HIP graph).  bz_batched_plan validates the
+ * items, picks each image's tiling (strip_rows: optional HOST array of `count`
+ * strip heights in rows, e.g. from an autotuner; NULL or entries < 1 select
+ * the default), orders the tiles largest-first, uploads the descriptors into
+ * `workspace` and SYNCHRONISES `stream` before returning (it is a set-up call,
+ * not part of the hot path).  bz_batched_run launches the single persistent
+ * kernel over a planned workspace and returns at once; it neither copies nor
+ * synchronises, so it can be captured in a graph and replayed.  The kernel
+ * leaves the workspace ready for the next run.  Runs of one workspace must not
+ * overlap in time.
+ */
+bz_status bz_batched_plan(const bz_item *items, int count, const int *strip_rows,
+                          void *workspace, size_t ws_bytes, bz_stream stream);
+bz_status bz_batched_run(void *workspace, bz_stream stream);
 
 /* Workspace bytes of the soft-Sauvola backward for B images of H x W. */
 size_t bz_soft_workspace_size(int B, int H, int W);

@@ -53,6 +53,34 @@ lib.bz_niblack.argtypes = [_P, _I, _I, _PD, _I, _I, _F, _P, _PD, _P, _P, _PD, _P
 lib.bz_window_quantile.restype = _I
 lib.bz_window_quantile.argtypes = [_P, _I, _I, _PD, _I, _I, _D, _P, _PD, _P, _PD, _P]
 
+
+class bz_item(ctypes.Structure):
+    """Mirror of the C ``bz_item`` descriptor."""
+    _fields_ = [("I", _P), ("mask", _P), ("mean", _P), ("std", _P),
+                ("H", _I), ("W", _I), ("h", _I), ("w", _I),
+                ("ld_I", _PD), ("ld_mask", _PD), ("ld_ms", _PD),
+                ("k", _F), ("R", _F), ("method", _I)]
+
+
+lib.bz_batched_workspace_size.restype = _SZ
+lib.bz_batched_workspace_size.argtypes = [_I]
+lib.bz_batched_plan.restype = _I
+lib.bz_batched_plan.argtypes = [ctypes.POINTER(bz_item), _I, ctypes.POINTER(_I), _P, _SZ, _P]
+lib.bz_batched_run.restype = _I
+lib.bz_batched_run.argtypes = [_P, _P]
+lib.bz_sauvola_batched.restype = _I
+lib.bz_sauvola_batched.argtypes = [ctypes.POINTER(bz_item), _I, _P, _SZ, _P]
+
+METHOD_SAUVOLA, METHOD_NIBLACK = 1, 2
+
+lib.bz_soft_workspace_size.restype = _SZ
+lib.bz_soft_workspace_size.argtypes = [_I, _I, _I]
+lib.bz_soft_sauvola_fwd.restype = _I
+lib.bz_soft_sauvola_fwd.argtypes = [_P, _I, _I, _I, _PD, _I, _I, _P, _P, _F, _P, _P]
+lib.bz_soft_sauvola_bwd.restype = _I
+lib.bz_soft_sauvola_bwd.argtypes = [_P, _P, _I, _I, _I, _PD, _I, _I, _P, _P, _F, _P, _P, _P, _P,
+                                    _SZ, _P]
+
 BZ_OK, BZ_ERR_INVALID, BZ_ERR_RANGE, BZ_ERR_ALIAS, BZ_ERR_WORKSPACE, BZ_ERR_HIP = range(6)
 
 
@@ -158,3 +186,137 @@ def window_quantile(img: torch.Tensor, h: int, w: int, q: float, with_mask: bool
                                   mask.data_ptr() if mask is not None else None, W,
                                   _stream(img)), "bz_window_quantile")
     return Q, mask
+
+
+class BatchPlan:
+    """A planned ragged batch: every image gets its own outputs, window and
+    parameters; ``run()`` binarizes all of them in ONE persistent kernel
+    launch, and ``capture()`` records that launch in a HIP graph for replay.
+
+    images: list of 2-D uint8 device tensors.  params: list of dicts with keys
+    h, w, k, R (optional, default 128), method ("sauvola" or "niblack"), stats
+    (optional bool, default True: also write mean/std).  strips: optional list
+    of per-image strip heights (rows), e.g. from ``tune.strips_for``.
+    """
+
+    def __init__(self, images, params, strips=None):
+        if len(images) != len(params) or not images:
+            raise ValueError("need one parameter dict per image")
+        dev = images[0].device
+        self.images, self.masks, self.means, self.stds = [], [], [], []
+        items = (bz_item * len(images))()
+        for i, (img, p) in enumerate(zip(images, params)):
+            img, H, W, ld = _image(img)
+            if img.device != dev:
+                raise ValueError("all images must be on one device")
+            self.images.append(img)
+            mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+            stats = p.get("stats", True)
+            mean = torch.empty((H, W), dtype=torch.float32, device=dev) if stats else None
+            std = torch.empty((H, W), dtype=torch.float32, device=dev) if stats else None
+            self.masks.append(mask)
+            self.means.append(mean)
+            self.stds.append(std)
+            method = p.get("method", "sauvola")
+            items[i] = bz_item(img.data_ptr(), mask.data_ptr(),
+                               mean.data_ptr() if mean is not None else None,
+                               std.data_ptr() if std is not None else None,
+                               H, W, int(p["h"]), int(p["w"]), ld, W, W if stats else 0,
+                               float(p["k"]), float(p.get("R", 128.0)),
+                               METHOD_SAUVOLA if method == "sauvola" else METHOD_NIBLACK)
+        self._items = items
+        n = len(images)
+        self.ws_bytes = int(lib.bz_batched_workspace_size(n))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        if strips is not None:
+            arr = (_I * n)(*[int(x) for x in strips])
+            sp = ctypes.cast(arr, ctypes.POINTER(_I))
+        else:
+            sp = None
+        _check(lib.bz_batched_plan(items, n, sp, self.workspace.data_ptr(), self.ws_bytes,
+                                   _stream(self.workspace)), "bz_batched_plan")
+        self.graph = None
+
+    def run(self):
+        """Enqueue the persistent launch on the current stream."""
+        _check(lib.bz_batched_run(self.workspace.data_ptr(), _stream(self.workspace)),
+               "bz_batched_run")
+
+    def capture(self):
+        """Record ``run()`` in a HIP graph (torch.cuda.CUDAGraph); later calls
+        to ``replay()`` launch it without host-side work."""
+        self.run()  # warm up the launch path outside capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def outputs(self):
+        return list(zip(self.masks, self.means, self.stds))
+
+
+def sauvola_batched(images, params, strips=None):
+    """One-shot ragged batch: plan, run once, return [(mask, mean, std), ...]."""
+    plan = BatchPlan(images, params, strips)
+    plan.run()
+    return plan.outputs()
+
+
+def _soft_inputs(I, k, R):
+    if I.dim() == 2:
+        I = I.unsqueeze(0)
+    if I.dim() != 3 or I.dtype != torch.float32 or not I.is_cuda:
+        raise ValueError("expected a (B, H, W) float32 device tensor")
+    I = I.contiguous()
+    B, H, W = I.shape
+    k = k.reshape(-1).to(torch.float32).contiguous()
+    R = R.reshape(-1).to(torch.float32).contiguous()
+    if k.numel() != B or R.numel() != 1 or not k.is_cuda or not R.is_cuda:
+        raise ValueError("k must hold B values and R one value, on the device")
+    return I, k, R, B, H, W
+
+
+class SoftSauvola(torch.autograd.Function):
+    """y = sigmoid((I - t) / tau) with the Sauvola threshold t of each pixel's
+    window; differentiable in I, k (one per image) and R.  Only I, k and R are
+    saved: the backward recomputes the window statistics."""
+
+    @staticmethod
+    def forward(ctx, I, k, R, h, w, tau):
+        I, k, R, B, H, W = _soft_inputs(I, k, R)
+        y = torch.empty_like(I)
+        _check(lib.bz_soft_sauvola_fwd(I.data_ptr(), B, H, W, W, int(h), int(w), k.data_ptr(),
+                                       R.data_ptr(), float(tau), y.data_ptr(), _stream(I)),
+               "bz_soft_sauvola_fwd")
+        ctx.save_for_backward(I, k, R)
+        ctx.win = (int(h), int(w), float(tau))
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        I, k, R = ctx.saved_tensors
+        h, w, tau = ctx.win
+        B, H, W = I.shape
+        gy = gy.reshape(B, H, W).to(torch.float32).contiguous()
+        gI = torch.empty_like(I)
+        gk = torch.empty_like(k)
+        gR = torch.empty_like(R)
+        nbytes = int(lib.bz_soft_workspace_size(B, H, W))
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=I.device)
+        _check(lib.bz_soft_sauvola_bwd(I.data_ptr(), gy.data_ptr(), B, H, W, W, h, w, k.data_ptr(),
+                                       R.data_ptr(), float(tau), gI.data_ptr(), gk.data_ptr(),
+                                       gR.data_ptr(), ws.data_ptr(), nbytes, _stream(I)),
+               "bz_soft_sauvola_bwd")
+        return gI, gk, gR, None, None, None
+
+
+def soft_sauvola(I, k, R, h: int, w: int, tau: float = 2.0):
+    """Differentiable soft Sauvola mask of a (B, H, W) float32 stack."""
+    return SoftSauvola.apply(I, k, R, h, w, tau)

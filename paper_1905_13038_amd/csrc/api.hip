@@ -8,6 +8,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 using namespace bz;
 
 namespace {
@@ -74,6 +77,10 @@ BoxJob make_job(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w)
     return j;
 }
 
+// Test and tuning hooks read from the environment at each call:
+// BZ_TILE_S / BZ_TILE_THREADS override the strip height / block size, and
+// BZ_FORCE_REFERENCE=1 decides every pixel with the binary64 reference
+// sequence instead of only those inside the float32 guard.
 int env_int(const char *name)
 {
     const char *e = getenv(name);
@@ -83,17 +90,14 @@ int env_int(const char *name)
 bz_status run_box(BoxJob &j, hipStream_t stream)
 {
     plan_box(j, env_int("BZ_TILE_S"), env_int("BZ_TILE_THREADS"));
-    // Test hook: BZ_FORCE_REFERENCE=1 decides every pixel with the binary64
-    // reference sequence instead of only those inside the float32 guard.
-    j.force_ref = env_int("BZ_FORCE_REFERENCE");
     if (inject_launch_fault()) return BZ_ERR_HIP;
     return hip_status(launch_box(j, stream));
 }
 
-// Threshold entry shared by Sauvola and Niblack.
-bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
-                         float k, float R, uint8_t *mask, ptrdiff_t ld_mask, float *mean,
-                         float *stdv, ptrdiff_t ld_ms, bz_stream stream)
+// Validate a Sauvola/Niblack call and fill its job (without tiling).
+bz_status make_threshold_job(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h,
+                             int w, float k, float R, uint8_t *mask, ptrdiff_t ld_mask,
+                             float *mean, float *stdv, ptrdiff_t ld_ms, BoxJob &j)
 {
     bz_status st = check_image(I, H, W, ld_I, h, w);
     if (st != BZ_OK) return st;
@@ -112,7 +116,7 @@ bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_
             overlaps(b, rm))
             return BZ_ERR_ALIAS;
     }
-    BoxJob j = make_job(I, H, W, ld_I, h, w);
+    j = make_job(I, H, W, ld_I, h, w);
     j.mode = mode;
     j.mask = mask;
     j.ldM = ld_mask;
@@ -122,6 +126,7 @@ bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_
     if (mode == MODE_SAUVOLA) {
         j.c0 = (float)(1.0 - (double)k);
         j.c1 = (float)((double)k / (double)R);
+        j.c2 = fabsf(j.c0) - j.c0;
     } else {
         j.c0 = 0.0f;
         j.c1 = k;
@@ -129,9 +134,31 @@ bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_
     j.kabs = fabsf(k);
     j.k64 = (double)k;
     j.R64 = (double)R;
-    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && aligned(mask, 4) && ld_mask % 4 == 0 &&
-                (mean == nullptr || (aligned(mean, 16) && aligned(stdv, 16) && ld_ms % 4 == 0));
+    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && W % 4 == 0;
+    j.force_ref = env_int("BZ_FORCE_REFERENCE");
+    return BZ_OK;
+}
+
+// Threshold entry shared by Sauvola and Niblack.
+bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
+                         float k, float R, uint8_t *mask, ptrdiff_t ld_mask, float *mean,
+                         float *stdv, ptrdiff_t ld_ms, bz_stream stream)
+{
+    BoxJob j;
+    const bz_status st =
+        make_threshold_job(mode, I, H, W, ld_I, h, w, k, R, mask, ld_mask, mean, stdv, ld_ms, j);
+    if (st != BZ_OK) return st;
     return run_box(j, (hipStream_t)stream);
+}
+
+// Default strip height of a batched image: long enough that the h-1 priming
+// rows stay a small part of a tile.
+int default_batch_strip(int h)
+{
+    int s = 2 * h;
+    if (s < 32) s = 32;
+    if (s > 128) s = 128;
+    return s;
 }
 
 }  // namespace
@@ -169,7 +196,7 @@ bz_status bz_window_sums(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, 
     j.S1 = S1;
     j.S2 = S2;
     j.ldS = ld_S;
-    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && aligned(S1, 16) && aligned(S2, 16) && ld_S % 4 == 0;
+    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && W % 4 == 0;
     return run_box(j, (hipStream_t)stream);
 }
 
@@ -188,8 +215,7 @@ bz_status bz_window_mean_std(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
     j.mean = mean;
     j.stdv = stdv;
     j.ldMS = ld_out;
-    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && aligned(mean, 16) && aligned(stdv, 16) &&
-                ld_out % 4 == 0;
+    j.aligned = aligned(I, 4) && ld_I % 4 == 0 && W % 4 == 0;
     return run_box(j, (hipStream_t)stream);
 }
 
@@ -243,6 +269,140 @@ bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
     j.ldM = mask ? ld_mask : 0;
     if (inject_launch_fault()) return BZ_ERR_HIP;
     return hip_status(launch_quantile(j, (hipStream_t)stream));
+}
+
+size_t bz_batched_workspace_size(int count)
+{
+    if (count < 0) return 0;
+    return batch_workspace_bytes(count);
+}
+
+bz_status bz_batched_plan(const bz_item *items, int count, const int *strip_rows, void *workspace,
+                          size_t ws_bytes, bz_stream stream)
+{
+    if (count < 1 || items == nullptr || workspace == nullptr) return BZ_ERR_INVALID;
+    if (!aligned(workspace, 64)) return BZ_ERR_INVALID;
+    if (ws_bytes < batch_workspace_bytes(count)) return BZ_ERR_WORKSPACE;
+    std::vector<BoxJob> jobs((size_t)count);
+    std::vector<int64_t> work((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const bz_item &it = items[i];
+        int mode;
+        if (it.method == BZ_METHOD_SAUVOLA) mode = MODE_SAUVOLA;
+        else if (it.method == BZ_METHOD_NIBLACK) mode = MODE_NIBLACK;
+        else return BZ_ERR_INVALID;
+        const bz_status st = make_threshold_job(mode, it.I, it.H, it.W, it.ld_I, it.h, it.w, it.k,
+                                                it.R, it.mask, it.ld_mask, it.mean, it.std,
+                                                it.ld_ms, jobs[(size_t)i]);
+        if (st != BZ_OK) return st;
+        int strip = (strip_rows != nullptr) ? strip_rows[i] : 0;
+        if (strip < 1) strip = default_batch_strip(it.h);
+        plan_box(jobs[(size_t)i], strip, BATCH_THREADS);
+        const BoxJob &j = jobs[(size_t)i];
+        // work of one tile: rows of the strip plus its priming rows, times
+        // the lanes' columns (priming rows cost about a twelfth of a row)
+        work[(size_t)i] = (int64_t)(12 * j.strip + j.h) * (int64_t)std::min(j.W, COLS_PER_LANE * BATCH_THREADS);
+    }
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return work[(size_t)x] > work[(size_t)y]; });
+    std::vector<char> blob(batch_workspace_bytes(count), 0);
+    BatchHeader *hdr = (BatchHeader *)blob.data();
+    hdr->next_tile = 0;
+    hdr->done = 0;
+    hdr->count = count;
+    BoxJob *dj = (BoxJob *)(hdr + 1);
+    int *prefix = (int *)(dj + count);
+    int64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        const BoxJob &j = jobs[(size_t)order[(size_t)i]];
+        dj[i] = j;
+        prefix[i] = (int)total;
+        total += (int64_t)j.ntx * j.nsy;
+        if (total > (int64_t)1 << 30) return BZ_ERR_RANGE;
+    }
+    prefix[count] = (int)total;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    hipError_t e = hipMemcpyAsync(workspace, blob.data(), blob.size(), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    return hip_status(e);
+}
+
+bz_status bz_batched_run(void *workspace, bz_stream stream)
+{
+    if (workspace == nullptr || !aligned(workspace, 64)) return BZ_ERR_INVALID;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    return hip_status(launch_box_batched(workspace, (hipStream_t)stream));
+}
+
+bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace, size_t ws_bytes,
+                             bz_stream stream)
+{
+    const bz_status st = bz_batched_plan(items, count, nullptr, workspace, ws_bytes, stream);
+    if (st != BZ_OK) return st;
+    return bz_batched_run(workspace, stream);
+}
+
+size_t bz_soft_workspace_size(int B, int H, int W)
+{
+    if (B < 1 || H < 1 || W < 1) return 0;
+    return soft_workspace_bytes(B, H, W);
+}
+
+namespace {
+
+bz_status check_soft(const float *I, int B, int H, int W, ptrdiff_t ld, int h, int w,
+                     const float *k, const float *R, float tau)
+{
+    if (I == nullptr || k == nullptr || R == nullptr) return BZ_ERR_INVALID;
+    if (B < 1 || H < 1 || W < 1 || h < 1 || w < 1 || ld < W) return BZ_ERR_INVALID;
+    if (h > MAX_WIN || w > MAX_WIN) return BZ_ERR_RANGE;
+    if (!isfinite(tau) || !(tau > 0.0f)) return BZ_ERR_INVALID;
+    if (!aligned(I, 4)) return BZ_ERR_INVALID;
+    if ((int64_t)B * H * (int64_t)ld > ((int64_t)1 << 40)) return BZ_ERR_RANGE;
+    return BZ_OK;
+}
+
+}  // namespace
+
+bz_status bz_soft_sauvola_fwd(const float *I, int B, int H, int W, ptrdiff_t ld, int h, int w,
+                              const float *k, const float *R, float tau, float *y,
+                              bz_stream stream)
+{
+    bz_status st = check_soft(I, B, H, W, ld, h, w, k, R, tau);
+    if (st != BZ_OK) return st;
+    if (y == nullptr || !aligned(y, 4)) return BZ_ERR_INVALID;
+    const Range in = span(I, B * H, W, ld, 4), out = span(y, B * H, W, ld, 4);
+    if (overlaps(in, out)) return BZ_ERR_ALIAS;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    return hip_status(launch_soft_fwd(I, B, H, W, ld, h, w, k, R, tau, y, (hipStream_t)stream));
+}
+
+bz_status bz_soft_sauvola_bwd(const float *I, const float *gy, int B, int H, int W, ptrdiff_t ld,
+                              int h, int w, const float *k, const float *R, float tau,
+                              float *gI, float *gk, float *gR, void *workspace, size_t ws_bytes,
+                              bz_stream stream)
+{
+    bz_status st = check_soft(I, B, H, W, ld, h, w, k, R, tau);
+    if (st != BZ_OK) return st;
+    if (gy == nullptr || gI == nullptr || gk == nullptr || gR == nullptr || workspace == nullptr)
+        return BZ_ERR_INVALID;
+    if (!aligned(gy, 4) || !aligned(gI, 4) || !aligned(gk, 4) || !aligned(gR, 4) ||
+        !aligned(workspace, 256))
+        return BZ_ERR_INVALID;
+    if (ws_bytes < soft_workspace_bytes(B, H, W)) return BZ_ERR_WORKSPACE;
+    const Range in = span(I, B * H, W, ld, 4), g = span(gy, B * H, W, ld, 4),
+                out = span(gI, B * H, W, ld, 4), wsr = span(workspace, 1, (int)0, 0, 1);
+    const Range wsr2{(uintptr_t)workspace, (uintptr_t)workspace + ws_bytes};
+    (void)wsr;
+    if (overlaps(in, out) || overlaps(g, out) || overlaps(wsr2, in) || overlaps(wsr2, g) ||
+        overlaps(wsr2, out))
+        return BZ_ERR_ALIAS;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    return hip_status(launch_soft_bwd(I, gy, B, H, W, ld, h, w, k, R, tau, gI, gk, gR, workspace,
+                                      (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -7,16 +7,47 @@
 // the column recurrence of Section 3.1 / Algorithm 1.  The horizontal window
 // sums are differences of a row prefix sum (S = P[j+r] - P[j-l]) built with a
 // DPP wavefront scan plus a cross-wave combine through LDS; unsigned 32-bit
-// wrap-around keeps the differences exact.  The threshold epilogue forms
-// n*S2 - S1^2 exactly (binary64 FMA on exact integers), derives float32 m and
-// s, and decides I < t in float32 with a proven error guard; pixels inside the
-// guard are re-decided with the binary64 reference sequence.
+// wrap-around keeps the differences exact.  Rows are handled in groups of R so
+// that one pair of workgroup barriers serves R rows.
+//
+// The threshold epilogue forms n*S2 - S1^2 exactly (binary64 FMA on exact
+// integers), derives float32 m and s, and decides I < t in float32 with an
+// error guard; pixels inside the guard are re-decided with the binary64
+// reference sequence.
+//
+// Two entry kernels share the tile body: k_box (one tile per workgroup, tiles
+// mapped XCD-contiguously) and k_box_batched (a persistent grid that claims
+// tiles of many images from an atomic counter, largest tiles first).
 #include "internal.hpp"
 
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 namespace bz {
 namespace {
+
+#ifndef BZ_ROWS_PER_GROUP
+#define BZ_ROWS_PER_GROUP 2
+#endif
+constexpr int ROWS_PER_GROUP = BZ_ROWS_PER_GROUP;
+
+// Layout of one LDS prefix row for NT threads.  Prefix index i (i = 0 is the
+// empty prefix, i = 1 .. 4 NT the tile's halo'd columns) lives at word
+// PREFIX_LPAD + i.  The PREFIX_LPAD words below index 0 hold zeros and the
+// PREFIX_RPAD words above index 4 NT repeat the last prefix, so a window that
+// reaches past either end of the tile reads the right value without an index
+// clamp (out-of-image columns contribute zero).  PREFIX_LPAD + 1 is a multiple
+// of 4, so each lane's indices 4t+1 .. 4t+4 form one aligned 16-byte group.
+constexpr int PREFIX_LPAD = 131;
+constexpr int PREFIX_RPAD = 128;
+__host__ __device__ constexpr int prefix_row_words(int NT)
+{
+    return PREFIX_LPAD + 1 + COLS_PER_LANE * NT + PREFIX_RPAD + 4;
+}
+// After the prefix rows: per group row, the gray levels of the row (one dword
+// per lane, NT words), then the wave totals.
 
 // Workgroup b is placed on XCD (b mod 8).  Give every XCD a contiguous range
 // of logical tiles so that the halo rows shared by vertically adjacent strips
@@ -58,24 +89,75 @@ __device__ __forceinline__ uint32_t row_scan16(uint32_t v)
     return v;
 }
 
-// Four pixels of one row starting at column c (c is a multiple of 4).
-// Out-of-image columns read as zero (Section 3.2's convention).
-template <bool AL>
-__device__ __forceinline__ uint32_t load4(const uint8_t *row, int c, int W)
+__device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
+
+// Raw buffer resources (base, num_records in bytes, stride 0).  Accesses at
+// offsets at or beyond num_records read zero and drop stores in hardware, so
+// image borders, out-of-image rows and lanes outside a tile need no per-lane
+// branch or select.  The last descriptor word is the raw-buffer format value
+// for gfx9-family chips.
+constexpr int RSRC_FLAGS = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes)
 {
-    if (c >= 0 && c + 4 <= W) {
-        if (AL) return *(const uint32_t *)(row + c);
-        return (uint32_t)row[c] | ((uint32_t)row[c + 1] << 8) | ((uint32_t)row[c + 2] << 16) |
-               ((uint32_t)row[c + 3] << 24);
-    }
-    uint32_t v = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (c + q >= 0 && c + q < W) v |= (uint32_t)row[c + q] << (8 * q);
-    return v;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             RSRC_FLAGS);
 }
 
-__device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
+// Reads the four pixels of a lane (columns cb .. cb+3) from any row; pixels
+// outside the image read as zero (Section 3.2's convention).  The row's
+// descriptor covers exactly its W bytes (none for rows outside [0, H)); the
+// lane's offset is its column.  In the aligned form (4-byte aligned rows, W a
+// multiple of 4) one dword load per lane; otherwise four byte loads.
+template <bool AL>
+struct LaneRow {
+    const uint8_t *base;
+    int64_t ld;
+    int W, H;
+    uint32_t off;  // this lane's first column (columns < 0 wrap to huge: zero)
+
+    __device__ __forceinline__ LaneRow(const uint8_t *I, int64_t ld_, int cb, int W_, int H_)
+        : base(I), ld(ld_), W(W_), H(H_), off((uint32_t)cb)
+    {
+    }
+
+    __device__ __forceinline__ uint32_t operator()(int row) const
+    {
+        const bool in = (row >= 0) && (row < H);
+        const __amdgpu_buffer_rsrc_t r =
+            rsrc(base + (int64_t)(in ? row : 0) * ld, in ? (uint32_t)W : 0u);
+        if (AL) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        uint32_t v = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            v |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)(off + q), 0, 0) << (8 * q);
+        return v;
+    }
+};
+
+// Add four rows (one dword per row, four columns each) to the column sums:
+// transpose the 4x4 bytes so each dword holds one column, then one SAD (sum)
+// and one DOT4 (sum of squares) per column.
+__device__ __forceinline__ void add4rows(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3,
+                                         uint32_t C[4], uint32_t D[4])
+{
+    const uint32_t a0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+    const uint32_t a1 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+    const uint32_t b0 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+    const uint32_t b1 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+    const uint32_t t0 = __builtin_amdgcn_perm(b0, a0, 0x05040100u);
+    const uint32_t t1 = __builtin_amdgcn_perm(b0, a0, 0x07060302u);
+    const uint32_t t2 = __builtin_amdgcn_perm(b1, a1, 0x05040100u);
+    const uint32_t t3 = __builtin_amdgcn_perm(b1, a1, 0x07060302u);
+    C[0] = __builtin_amdgcn_sad_u8(t0, 0u, C[0]);
+    C[1] = __builtin_amdgcn_sad_u8(t1, 0u, C[1]);
+    C[2] = __builtin_amdgcn_sad_u8(t2, 0u, C[2]);
+    C[3] = __builtin_amdgcn_sad_u8(t3, 0u, C[3]);
+    D[0] = __builtin_amdgcn_udot4(t0, t0, D[0], false);
+    D[1] = __builtin_amdgcn_udot4(t1, t1, D[1], false);
+    D[2] = __builtin_amdgcn_udot4(t2, t2, D[2], false);
+    D[3] = __builtin_amdgcn_udot4(t3, t3, D[3], false);
+}
 
 // The binary64 reference decision I < t (each operation rounded once).
 __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S1, uint32_t S2,
@@ -109,55 +191,53 @@ __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S
 constexpr float GUARD = 3.814697265625e-06f;  // 2^-18
 
 template <int MODE, bool AL>
-__global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
+__device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
-    extern __shared__ uint32_t smem[];
+    constexpr int R = ROWS_PER_GROUP;
     const int NT = blockDim.x;
-    const int NH = COLS_PER_LANE * NT;   // halo'd columns of the tile
-    const int PS = NH + 4;               // prefix row: [0] = 0, [1..NH]
-    uint32_t *Pc = smem;                 // [2][PS]
-    uint32_t *Pd = smem + 2 * PS;        // [2][PS]
-    uint32_t *Tc = smem + 4 * PS;        // [2][MAX_WAVES] wave totals
-    uint32_t *Td = Tc + 2 * MAX_WAVES;
+    const int PS = prefix_row_words(NT);
+    uint32_t *Gray = smem + R * 2 * PS;   // [R][NT] gray levels of the group's rows
+    uint32_t *Tot = Gray + R * NT;        // [R][2][MAX_WAVES] wave totals
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = NT >> 6;
 
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = L / a.nsy;
-    const int sy = L - tx * a.nsy;
     const int x0 = tx * a.tile_w;
     const int x1 = min(x0 + a.tile_w, a.W);
     const int y0 = sy * a.strip;
     const int y1 = min(y0 + a.strip, a.H);
     const int xh = (tx == 0) ? 0 : x0 - a.halo_l;
-    const int cb = xh + COLS_PER_LANE * tid;  // first column of this lane
-
     const int H = a.H, W = a.W, o = a.o, u = a.u;
+    // vertical pass: lane owns the four columns cb .. cb+3
+    const int cb = xh + COLS_PER_LANE * tid;
+    const LaneRow<AL> ld(a.I, a.ldI, cb, W, H);
 
-    if (tid == 0) {
-        Pc[0] = 0; Pc[PS] = 0; Pd[0] = 0; Pd[PS] = 0;
+    // zero the left pads (and index 0) of every prefix row once
+    for (int i = tid; i < R * 2 * (PREFIX_LPAD + 1); i += NT) {
+        const int row = i / (PREFIX_LPAD + 1);
+        smem[row * PS + (i - row * (PREFIX_LPAD + 1))] = 0u;
     }
 
-    // Per-column constants: prefix indices of the window's right end and of
-    // the column just left of it (clamped: prefixes are flat outside the
-    // image), the column count nc and its reciprocal.
-    int ai[4], bi[4], nc[4];
+    // Epilogue: wave w covers the same 256 columns as in the vertical pass,
+    // but lane t takes columns t, t+64, t+128, t+192 of them, so that the
+    // prefix reads of a wavefront hit consecutive LDS words (no bank
+    // conflicts) and each store instruction writes 64 consecutive elements.
+    const int ec0 = xh + 256 * wave + lane;  // column k is ec0 + 64 k
+    const int ai0 = PREFIX_LPAD + ec0 + a.r - xh + 1;  // prefix word of j + r
+    const int bi0 = PREFIX_LPAD + ec0 - a.l - xh + 1;  // prefix word of j - l
+    int nc[4];
     float rnc[4];
     bool valid[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int j = cb + k;
+        const int j = ec0 + 64 * k;
         valid[k] = (j >= x0) && (j < x1);
-        const int ar = min(j + a.r, W - 1);
-        const int bl = max(j - a.l, -1);
-        ai[k] = valid[k] ? ar - xh + 1 : 0;
-        bi[k] = valid[k] ? bl - xh + 1 : 0;
-        nc[k] = ar - bl;
-        rnc[k] = valid[k] ? 1.0f / (float)nc[k] : 0.0f;
+        nc[k] = valid[k] ? min(j + a.r, W - 1) - max(j - a.l, -1) : 1;
+        rnc[k] = 1.0f / (float)nc[k];
     }
+    const bool any_valid = valid[0] || valid[1] || valid[2] || valid[3];
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
@@ -165,170 +245,254 @@ __global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
         const int p0 = max(y0 - o, 0);
         const int p1 = min(y0 + u - 1, H - 1);
         int row = p0;
-        // four rows at a time: transpose the 4x4 bytes so each dword holds one
-        // column, then one SAD (sum) and one DOT4 (sum of squares) per column
-        for (; row + 3 <= p1; row += 4) {
-            const uint32_t r0 = load4<AL>(a.I + (int64_t)row * a.ldI, cb, W);
-            const uint32_t r1 = load4<AL>(a.I + (int64_t)(row + 1) * a.ldI, cb, W);
-            const uint32_t r2 = load4<AL>(a.I + (int64_t)(row + 2) * a.ldI, cb, W);
-            const uint32_t r3 = load4<AL>(a.I + (int64_t)(row + 3) * a.ldI, cb, W);
-            const uint32_t x0l = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
-            const uint32_t x1l = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
-            const uint32_t y0l = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
-            const uint32_t y1l = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
-            const uint32_t t0 = __builtin_amdgcn_perm(y0l, x0l, 0x05040100u);
-            const uint32_t t1 = __builtin_amdgcn_perm(y0l, x0l, 0x07060302u);
-            const uint32_t t2 = __builtin_amdgcn_perm(y1l, x1l, 0x05040100u);
-            const uint32_t t3 = __builtin_amdgcn_perm(y1l, x1l, 0x07060302u);
-            C[0] = __builtin_amdgcn_sad_u8(t0, 0u, C[0]);
-            C[1] = __builtin_amdgcn_sad_u8(t1, 0u, C[1]);
-            C[2] = __builtin_amdgcn_sad_u8(t2, 0u, C[2]);
-            C[3] = __builtin_amdgcn_sad_u8(t3, 0u, C[3]);
-            D[0] = __builtin_amdgcn_udot4(t0, t0, D[0], false);
-            D[1] = __builtin_amdgcn_udot4(t1, t1, D[1], false);
-            D[2] = __builtin_amdgcn_udot4(t2, t2, D[2], false);
-            D[3] = __builtin_amdgcn_udot4(t3, t3, D[3], false);
+        // batches of sixteen rows: all sixteen loads in flight, then four
+        // SAD/DOT4 groups
+        for (; row + 15 <= p1; row += 16) {
+            uint32_t v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = ld(row + q);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                add4rows(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], C, D);
         }
-        for (; row <= p1; ++row) {
-            const uint32_t v = load4<AL>(a.I + (int64_t)row * a.ldI, cb, W);
+        for (; row + 3 <= p1; row += 4) add4rows(ld(row), ld(row + 1), ld(row + 2), ld(row + 3), C, D);
+        for (; row <= p1; ++row) add4rows(ld(row), 0u, 0u, 0u, C, D);
+    }
+
+    // ---- march down the strip, R rows per group ----
+    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
+    // next group's entering, leaving and centre-row dwords; the centre rows
+    // go through LDS to reach the epilogue's column assignment
+    uint32_t na[R], nb[R], ni[R];
+    auto load_group = [&](int yg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            na[r] = ld(yg + r + u);
+            nb[r] = ld(yg + r - o);
+            if (need_i) ni[r] = ld(yg + r);
+        }
+    };
+    load_group(y0);
+    const uint8_t *gray_b = (const uint8_t *)Gray;
+    for (int yg = y0; yg < y1; yg += R) {
+        uint32_t va[R], vb[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            va[r] = na[r];
+            vb[r] = nb[r];
+            if (need_i) Gray[r * NT + tid] = ni[r];
+        }
+        if (yg + R < y1) load_group(yg + R);  // prefetch the next group
+        // column recurrence and per-lane prefixes for each row of the group
+        uint32_t pc[R][4], pd[R][4], sc[R], sd[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (yg + r < y1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int ak = (int)byte_of(va[r], k), bk = (int)byte_of(vb[r], k);
+                    const int dk = ak - bk;
+                    C[k] += (uint32_t)dk;
+                    D[k] += (uint32_t)(dk * (ak + bk));
+                }
+            }
+            pc[r][0] = C[0];
+            pc[r][1] = pc[r][0] + C[1];
+            pc[r][2] = pc[r][1] + C[2];
+            pc[r][3] = pc[r][2] + C[3];
+            pd[r][0] = D[0];
+            pd[r][1] = pd[r][0] + D[1];
+            pd[r][2] = pd[r][1] + D[2];
+            pd[r][3] = pd[r][2] + D[3];
+            sc[r] = wave_scan(pc[r][3]);
+            sd[r] = wave_scan(pd[r][3]);
+            if (lane == 63) {
+                Tot[(r * 2) * MAX_WAVES + wave] = sc[r];
+                Tot[(r * 2 + 1) * MAX_WAVES + wave] = sd[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t wc = (lane < nwaves) ? Tot[(r * 2) * MAX_WAVES + lane] : 0u;
+            uint32_t wd = (lane < nwaves) ? Tot[(r * 2 + 1) * MAX_WAVES + lane] : 0u;
+            wc = row_scan16(wc);
+            wd = row_scan16(wd);
+            const uint32_t oc = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wc, wave - 1) : 0u;
+            const uint32_t od = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wd, wave - 1) : 0u;
+            const uint32_t ec_ = sc[r] - pc[r][3] + oc, ed_ = sd[r] - pd[r][3] + od;
+            uint32_t *prc = smem + r * 2 * PS + PREFIX_LPAD + 1;  // index 1
+            uint32_t *prd = prc + PS;
+            *(uint4 *)(prc + COLS_PER_LANE * tid) =
+                make_uint4(pc[r][0] + ec_, pc[r][1] + ec_, pc[r][2] + ec_, pc[r][3] + ec_);
+            *(uint4 *)(prd + COLS_PER_LANE * tid) =
+                make_uint4(pd[r][0] + ed_, pd[r][1] + ed_, pd[r][2] + ed_, pd[r][3] + ed_);
+            if (wave == nwaves - 1) {  // right pad: repeat the tile total
+                const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)wc, nwaves - 1);
+                const uint32_t td = (uint32_t)__builtin_amdgcn_readlane((int)wd, nwaves - 1);
+                prc[COLS_PER_LANE * NT + lane] = tc;
+                prc[COLS_PER_LANE * NT + 64 + lane] = tc;
+                prd[COLS_PER_LANE * NT + lane] = td;
+                prd[COLS_PER_LANE * NT + 64 + lane] = td;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yg + r;
+            if (y >= y1 || !any_valid) continue;
+            const uint32_t *pa = smem + r * 2 * PS + ai0;  // this lane's window ends
+            const uint32_t *pb = smem + r * 2 * PS + bi0;
+            uint32_t S1[4], S2[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t b = byte_of(v, k);
-                C[k] += b;
-                D[k] += b * b;
+                S1[k] = pa[64 * k] - pb[64 * k];
+                S2[k] = pa[PS + 64 * k] - pb[PS + 64 * k];
             }
-        }
-    }
-
-    // ---- march down the strip ----
-    const bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
-    uint32_t na = 0, nb = 0, ni = 0;
-    {
-        const int ra = y0 + u, rb = y0 - o;
-        if (ra < H) na = load4<AL>(a.I + (int64_t)ra * a.ldI, cb, W);
-        if (rb >= 0) nb = load4<AL>(a.I + (int64_t)rb * a.ldI, cb, W);
-        if (need_i) ni = load4<AL>(a.I + (int64_t)y0 * a.ldI, cb, W);
-    }
-    for (int y = y0; y < y1; ++y) {
-        const int buf = (y - y0) & 1;
-        const uint32_t va = na, vb = nb, vi = ni;
-        if (y + 1 < y1) {  // prefetch the next row's three dwords
-            const int ra = y + 1 + u, rb = y + 1 - o;
-            na = (ra < H) ? load4<AL>(a.I + (int64_t)ra * a.ldI, cb, W) : 0u;
-            nb = (rb >= 0) ? load4<AL>(a.I + (int64_t)rb * a.ldI, cb, W) : 0u;
-            if (need_i) ni = load4<AL>(a.I + (int64_t)(y + 1) * a.ldI, cb, W);
-        }
-        // column recurrence: add the entering row, drop the leaving row
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ak = (int)byte_of(va, k), bk = (int)byte_of(vb, k);
-            const int dk = ak - bk;
-            C[k] += (uint32_t)dk;
-            D[k] += (uint32_t)(dk * (ak + bk));
-        }
-        // row prefix sums of C and D over the tile (mod 2^32)
-        const uint32_t pc0 = C[0], pc1 = pc0 + C[1], pc2 = pc1 + C[2], pc3 = pc2 + C[3];
-        const uint32_t pd0 = D[0], pd1 = pd0 + D[1], pd2 = pd1 + D[2], pd3 = pd2 + D[3];
-        const uint32_t sc = wave_scan(pc3);
-        const uint32_t sd = wave_scan(pd3);
-        if (lane == 63) {
-            Tc[buf * MAX_WAVES + wave] = sc;
-            Td[buf * MAX_WAVES + wave] = sd;
-        }
-        __syncthreads();
-        uint32_t wc = (lane < nwaves) ? Tc[buf * MAX_WAVES + lane] : 0u;
-        uint32_t wd = (lane < nwaves) ? Td[buf * MAX_WAVES + lane] : 0u;
-        wc = row_scan16(wc);
-        wd = row_scan16(wd);
-        const uint32_t oc = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wc, wave - 1) : 0u;
-        const uint32_t od = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wd, wave - 1) : 0u;
-        const uint32_t ec = sc - pc3 + oc, ed = sd - pd3 + od;
-        uint32_t *pc = Pc + buf * PS + 1 + COLS_PER_LANE * tid;
-        uint32_t *pd = Pd + buf * PS + 1 + COLS_PER_LANE * tid;
-        pc[0] = pc0 + ec; pc[1] = pc1 + ec; pc[2] = pc2 + ec; pc[3] = pc3 + ec;
-        pd[0] = pd0 + ed; pd[1] = pd1 + ed; pd[2] = pd2 + ed; pd[3] = pd3 + ed;
-        __syncthreads();
-
-        const uint32_t *Pcb = Pc + buf * PS;
-        const uint32_t *Pdb = Pd + buf * PS;
-        uint32_t S1[4], S2[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            S1[k] = Pcb[ai[k]] - Pcb[bi[k]];
-            S2[k] = Pdb[ai[k]] - Pdb[bi[k]];
-        }
-        const bool full = valid[0] && valid[3];
-
-        if (MODE == MODE_SUMS) {
-            uint32_t *o1 = a.S1 + (int64_t)y * a.ldS + cb;
-            uint32_t *o2 = a.S2 + (int64_t)y * a.ldS + cb;
-            if (AL && full) {
-                *(uint4 *)o1 = make_uint4(S1[0], S1[1], S1[2], S1[3]);
-                *(uint4 *)o2 = make_uint4(S2[0], S2[1], S2[2], S2[3]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (valid[k]) { o1[k] = S1[k]; o2[k] = S2[k]; }
+            // gray levels of the lane's four epilogue columns (byte offsets
+            // relative to the tile's first halo'd column)
+            uint32_t vi = 0u;
+            if (need_i) {
+                const uint8_t *gp = gray_b + r * NT * 4 + (ec0 - xh);
+                vi = (uint32_t)gp[0] | ((uint32_t)gp[64] << 8) | ((uint32_t)gp[128] << 16) |
+                     ((uint32_t)gp[192] << 24);
             }
-            continue;
-        }
 
-        // moments
-        const int nr = min(y + u, H - 1) - max(y - o, -1);
-        const float rnr = (nr == a.h) ? a.rh : 1.0f / (float)nr;
-        const double nrd = (double)nr;
-        float m[4], s[4];
+            // output descriptors cover this tile's columns [x0, x1) of row y;
+            // lanes outside it fall out of range and store nothing
+            const uint32_t ow = (uint32_t)(x1 - x0);
+            const int eo = ec0 - x0;  // negative for left-halo lanes: out of range
+            if (MODE == MODE_SUMS) {
+                const __amdgpu_buffer_rsrc_t r1 = rsrc(a.S1 + (int64_t)y * a.ldS + x0, 4 * ow);
+                const __amdgpu_buffer_rsrc_t r2 = rsrc(a.S2 + (int64_t)y * a.ldS + x0, 4 * ow);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float rn = rnr * rnc[k];
-            m[k] = (float)S1[k] * rn;
-            const double s1d = (double)S1[k];
-            // n*S2 - S1^2: every term is an integer below 2^53, so exact
-            const double vn = __builtin_fma(nrd * (double)nc[k], (double)S2[k], -(s1d * s1d));
-            s[k] = __builtin_amdgcn_sqrtf((float)vn) * rn;
-        }
-        if (a.mean != nullptr) {
-            float *om = a.mean + (int64_t)y * a.ldMS + cb;
-            float *os = a.stdv + (int64_t)y * a.ldMS + cb;
-            if (AL && full) {
-                *(float4 *)om = make_float4(m[0], m[1], m[2], m[3]);
-                *(float4 *)os = make_float4(s[0], s[1], s[2], s[3]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (valid[k]) { om[k] = m[k]; os[k] = s[k]; }
+                for (int k = 0; k < 4; ++k) {
+                    __builtin_amdgcn_raw_buffer_store_b32(S1[k], r1, 4 * (eo + 64 * k), 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(S2[k], r2, 4 * (eo + 64 * k), 0, 0);
+                }
+                continue;
             }
-        }
-        if (MODE == MODE_MEANSTD) continue;
 
-        // threshold and mask
-        uint32_t word = 0;
+            // moments: n = nr * nc; n*S2 - S1^2 is formed exactly in binary64
+            // (every term is an integer below 2^53)
+            const int nr = min(y + u, H - 1) - max(y - o, -1);
+            const float rnr = (nr == a.h) ? a.rh : __builtin_amdgcn_rcpf((float)nr);
+            float m[4], s[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float t, mag;
-            if (MODE == MODE_SAUVOLA) {
-                t = m[k] * __builtin_fmaf(a.c1, s[k], a.c0);
-                mag = m[k] * __builtin_fmaf(a.c1, s[k], __builtin_fabsf(a.c0));
-            } else {
-                t = __builtin_fmaf(a.c1, s[k], m[k]);
-                mag = __builtin_fmaf(a.kabs, s[k], m[k]);
+            for (int k = 0; k < 4; ++k) {
+                const float rn = rnr * rnc[k];
+                m[k] = (float)S1[k] * rn;
+                const double s1d = (double)S1[k];
+                const double nd = (double)(uint32_t)(nr * nc[k]);
+                const double vn = __builtin_fma(nd, (double)S2[k], -(s1d * s1d));
+                s[k] = __builtin_amdgcn_sqrtf((float)vn) * rn;
             }
-            const uint32_t iv = byte_of(vi, k);
-            const float d = (float)iv - t;
-            uint32_t bit = (d < 0.0f) ? 1u : 0u;
-            if (valid[k] && (a.force_ref || __builtin_fabsf(d) <= GUARD * mag)) {
-                const int64_t n = (int64_t)nr * nc[k];
-                bit = below_reference(iv, S1[k], S2[k], n, MODE, a.k64, a.R64) ? 1u : 0u;
+            if (a.mean != nullptr) {
+                const __amdgpu_buffer_rsrc_t rm = rsrc(a.mean + (int64_t)y * a.ldMS + x0, 4 * ow);
+                const __amdgpu_buffer_rsrc_t rs = rsrc(a.stdv + (int64_t)y * a.ldMS + x0, 4 * ow);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(m[k]), rm, 4 * (eo + 64 * k), 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s[k]), rs, 4 * (eo + 64 * k), 0, 0);
+                }
             }
-            word |= bit << (8 * k);
-        }
-        uint8_t *omk = a.mask + (int64_t)y * a.ldM + cb;
-        if (AL && full) {
-            *(uint32_t *)omk = word;
-        } else {
+            if (MODE == MODE_MEANSTD) continue;
+
+            // threshold and mask: the sign bit of d = I - t is the mask bit
+            // (I - t rounds to +0 when equal); pixels within the guard are
+            // re-decided with the binary64 sequence (one call site, rare)
+            const __amdgpu_buffer_rsrc_t rk = rsrc(a.mask + (int64_t)y * a.ldM + x0, ow);
+            uint32_t bits[4];
+            uint32_t near = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float t, mag;
+                if (MODE == MODE_SAUVOLA) {
+                    t = m[k] * __builtin_fmaf(a.c1, s[k], a.c0);
+                    mag = __builtin_fmaf(a.c2, m[k], t);  // m (c1 s + |c0|)
+                } else {
+                    t = __builtin_fmaf(a.c1, s[k], m[k]);
+                    mag = __builtin_fmaf(a.kabs, s[k], m[k]);
+                }
+                const float d = (float)byte_of(vi, k) - t;
+                bits[k] = __float_as_uint(d) >> 31;
+                if (valid[k] && (a.force_ref || __builtin_fabsf(d) <= GUARD * mag)) near |= 1u << k;
+            }
+            while (near != 0) {
+                const int k = __builtin_ctz(near);
+                near &= near - 1;
+                const uint32_t s1 = (k == 0) ? S1[0] : (k == 1) ? S1[1] : (k == 2) ? S1[2] : S1[3];
+                const uint32_t s2 = (k == 0) ? S2[0] : (k == 1) ? S2[1] : (k == 2) ? S2[2] : S2[3];
+                const int nck = (k == 0) ? nc[0] : (k == 1) ? nc[1] : (k == 2) ? nc[2] : nc[3];
+                const uint32_t iv = byte_of(vi >> (8 * k), 0);
+                const uint32_t bit =
+                    below_reference(iv, s1, s2, (int64_t)nr * nck, MODE, a.k64, a.R64) ? 1u : 0u;
+                bits[0] = (k == 0) ? bit : bits[0];
+                bits[1] = (k == 1) ? bit : bits[1];
+                bits[2] = (k == 2) ? bit : bits[2];
+                bits[3] = (k == 3) ? bit : bits[3];
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (valid[k]) omk[k] = (uint8_t)byte_of(word, k);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[k], rk, eo + 64 * k, 0, 0);
+        }
+    }
+}
+
+template <int MODE, bool AL>
+__global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
+{
+    extern __shared__ uint32_t smem[];
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = L / a.nsy;
+    box_tile<MODE, AL>(a, tx, L - tx * a.nsy, smem);
+}
+
+// Persistent grid over the tiles of a ragged batch.  Tiles are numbered in the
+// order of the job array (largest per-tile work first); prefix[i] is the first
+// tile of job i and prefix[count] the total.  The last workgroup to finish
+// resets the counters, so the next launch (or graph replay) starts from zero
+// without a memset.
+__global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_tile;
+    const int count = hdr->count;
+    const BoxJob *jobs = (const BoxJob *)(hdr + 1);
+    const int *prefix = (const int *)(jobs + count);
+    const int total = prefix[count];
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&hdr->next_tile, 1u);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const BoxJob &a = jobs[lo];
+        const int local = t - prefix[lo];
+        const int tx = local / a.nsy;
+        const int sy = local - tx * a.nsy;
+        if (a.mode == MODE_SAUVOLA) {
+            if (a.aligned) box_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
+            else box_tile<MODE_SAUVOLA, false>(a, tx, sy, smem);
+        } else {
+            if (a.aligned) box_tile<MODE_NIBLACK, true>(a, tx, sy, smem);
+            else box_tile<MODE_NIBLACK, false>(a, tx, sy, smem);
+        }
+        __syncthreads();  // the tile's LDS is free before the next claim
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&hdr->done, 1u);
+        if (prev == gridDim.x - 1) {
+            atomicExch(&hdr->next_tile, 0u);
+            atomicExch(&hdr->done, 0u);
         }
     }
 }
@@ -337,7 +501,7 @@ template <int MODE, bool AL>
 hipError_t launch_mode(const BoxJob &a, hipStream_t stream)
 {
     const int NT = a.threads;
-    const size_t lds = (size_t)(4 * (COLS_PER_LANE * NT + 4) + 4 * MAX_WAVES) * sizeof(uint32_t);
+    const size_t lds = (size_t)box_lds_words(NT) * sizeof(uint32_t);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_box<MODE, AL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -349,6 +513,11 @@ hipError_t launch_mode(const BoxJob &a, hipStream_t stream)
 }
 
 }  // namespace
+
+int box_lds_words(int NT)
+{
+    return ROWS_PER_GROUP * (2 * prefix_row_words(NT) + NT + 2 * MAX_WAVES);
+}
 
 void plan_box(BoxJob &a, int strip_override, int threads_override)
 {
@@ -365,16 +534,15 @@ void plan_box(BoxJob &a, int strip_override, int threads_override)
     } else {
         NT = MAX_THREADS;
     }
-    const int NH = COLS_PER_LANE * NT;
     a.threads = NT;
-    if (a.W <= NH) {
+    if (a.W <= COLS_PER_LANE * NT) {
         a.tile_w = a.W;
         a.ntx = 1;
         a.halo_l = 0;
     } else {
         a.halo_l = ((a.l - 1) + 3) & ~3;
-        a.tile_w = (NH - a.halo_l - a.r) & ~3;
-        if (a.tile_w < 256) {  // too narrow for the window: use the widest block
+        a.tile_w = (COLS_PER_LANE * NT - a.halo_l - a.r) & ~3;
+        if (a.tile_w < 4) {  // window wider than the block: use the widest block
             a.threads = NT = MAX_THREADS;
             a.tile_w = (COLS_PER_LANE * NT - a.halo_l - a.r) & ~3;
         }
@@ -406,6 +574,43 @@ hipError_t launch_box(const BoxJob &a, hipStream_t stream)
     case MODE_NIBLACK: return al ? launch_mode<MODE_NIBLACK, true>(a, stream) : launch_mode<MODE_NIBLACK, false>(a, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+size_t batch_workspace_bytes(int count)
+{
+    const size_t raw = sizeof(BatchHeader) + (size_t)count * sizeof(BoxJob) + (size_t)(count + 1) * sizeof(int);
+    return (raw + 255) & ~(size_t)255;
+}
+
+int batch_grid()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= device) cache.resize(device + 1, 0);
+    if (cache[device] == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        const size_t lds = (size_t)box_lds_words(BATCH_THREADS) * sizeof(uint32_t);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_box_batched, BATCH_THREADS, lds) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+        cache[device] = cus * per_cu;
+    }
+    return cache[device];
+}
+
+hipError_t launch_box_batched(void *workspace, hipStream_t stream)
+{
+    const size_t lds = (size_t)box_lds_words(BATCH_THREADS) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_box_batched, dim3(batch_grid()), dim3(BATCH_THREADS), lds, stream,
+                       (BatchHeader *)workspace);
+    return hipGetLastError();
 }
 
 }  // namespace bz

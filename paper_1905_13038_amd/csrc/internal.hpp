@@ -37,6 +37,7 @@ struct BoxJob {
     int64_t ldM;
     // threshold parameters: float fast path and binary64 canonical path
     float c0, c1;          // Sauvola: 1 - k, k / R; Niblack: unused, c1 = k
+    float c2;              // Sauvola: |c0| - c0 (guard magnitude m (c1 s + |c0|) = t + c2 m)
     float kabs;            // |k| (Niblack guard)
     double k64, R64;
     float rh;              // 1 / h, rounded (interior-row reciprocal)
@@ -57,6 +58,23 @@ void plan_box(BoxJob &job, int strip_override, int threads_override);
 // Enqueue the box-statistics kernel for one planned job.
 hipError_t launch_box(const BoxJob &job, hipStream_t stream);
 
+// LDS words one box tile uses with NT threads.
+int box_lds_words(int NT);
+
+// Ragged batches: one persistent launch over the tiles of many images.
+// Workspace layout: BatchHeader, BoxJob jobs[count], int prefix[count + 1]
+// (prefix[i] = first tile of job i, prefix[count] = total tiles).
+constexpr int BATCH_THREADS = 256;
+struct alignas(64) BatchHeader {
+    unsigned int next_tile;  // tile counter (zero between launches)
+    unsigned int done;       // finished workgroups (zero between launches)
+    int count;               // number of jobs
+    int pad[13];
+};
+size_t batch_workspace_bytes(int count);
+hipError_t launch_box_batched(void *workspace, hipStream_t stream);
+int batch_grid();
+
 // Windowed quantile (Section 3.4).
 struct QuantJob {
     const uint8_t *I;
@@ -70,5 +88,13 @@ struct QuantJob {
     int64_t ldM;
 };
 hipError_t launch_quantile(const QuantJob &job, hipStream_t stream);
+
+// Differentiable Sauvola (binary64 window sums over float32 images).
+size_t soft_workspace_bytes(int B, int H, int W);
+hipError_t launch_soft_fwd(const float *I, int B, int H, int W, int64_t ld, int h, int w,
+                           const float *k, const float *R, float tau, float *y, hipStream_t st);
+hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W, int64_t ld, int h,
+                           int w, const float *k, const float *R, float tau, float *gI, float *gk,
+                           float *gR, void *ws, hipStream_t st);
 
 }  // namespace bz
