@@ -42,7 +42,8 @@ typedef void *bz_stream; /* hipStream_t */
 typedef enum {
     BZ_OK = 0,
     BZ_ERR_INVALID = 1,   /* bad size, stride, pointer or parameter */
-    BZ_ERR_RANGE = 2,     /* h or w above 257, or sizes beyond 2^31 */
+    BZ_ERR_RANGE = 2,     /* h or w above 257, sizes beyond 2^31, or h rows of the
+                             image (h * ld + W bytes) spanning 2^31 bytes or more */
     BZ_ERR_ALIAS = 3,     /* an output overlaps the input */
     BZ_ERR_WORKSPACE = 4, /* caller workspace too small */
     BZ_ERR_HIP = 5        /* the HIP runtime reported an error */

@@ -51,6 +51,9 @@ bz_status check_image(const void *I, int H, int W, ptrdiff_t ld, int h, int w)
     if (ld < W) return BZ_ERR_INVALID;
     if (h > MAX_WIN || w > MAX_WIN) return BZ_ERR_RANGE;
     if ((int64_t)H * (int64_t)ld > ((int64_t)1 << 46)) return BZ_ERR_RANGE;
+    // the rows one window spans must lie within 2^31 bytes (a kernel reads a
+    // strip of rows through one buffer descriptor)
+    if ((int64_t)h * (int64_t)ld + W >= ((int64_t)1 << 31)) return BZ_ERR_RANGE;
     return BZ_OK;
 }
 
@@ -73,7 +76,6 @@ BoxJob make_job(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w)
     j.W = W;
     j.h = h;
     j.w = w;
-    j.rh = 1.0f / (float)h;
     return j;
 }
 
@@ -126,7 +128,6 @@ bz_status make_threshold_job(int mode, const uint8_t *I, int H, int W, ptrdiff_t
     if (mode == MODE_SAUVOLA) {
         j.c0 = (float)(1.0 - (double)k);
         j.c1 = (float)((double)k / (double)R);
-        j.c2 = fabsf(j.c0) - j.c0;
     } else {
         j.c0 = 0.0f;
         j.c1 = k;

@@ -22,6 +22,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -98,42 +99,55 @@ __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8
 // for gfx9-family chips.
 constexpr int RSRC_FLAGS = 0x00020000;
 
+// Cache policy of the output stores: non-temporal.  Outputs are written once
+// and not read back by the kernel; streaming them keeps the L2 for the input
+// rows the strips share and raised the store rate of this access pattern by
+// about 40% in measurements on MI355X.
+constexpr int STORE_NT = 2;
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
                                              RSRC_FLAGS);
 }
 
-// Reads the four pixels of a lane (columns cb .. cb+3) from any row; pixels
-// outside the image read as zero (Section 3.2's convention).  The row's
-// descriptor covers exactly its W bytes (none for rows outside [0, H)); the
-// lane's offset is its column.  In the aligned form (4-byte aligned rows, W a
-// multiple of 4) one dword load per lane; otherwise four byte loads.
+// Reads the four pixels of a lane (columns cb .. cb+3) of one row through a
+// descriptor d over whole rows from a first row r0, the row chosen by the
+// scalar offset so = (row - r0) * ld.  Pixels outside the image read as zero
+// (Section 3.2's convention): a lane's offset is its column, replaced by 2^31
+// where the column lies outside [0, W), and rows outside the image are read
+// through a descriptor of no bytes.  Every valid offset is below W and every
+// invalid one at least 2^31, above any descriptor size used here, so the
+// result does not depend on whether the hardware includes the scalar offset
+// in its range check.  In the aligned form (4-byte aligned rows, W a multiple
+// of 4) one dword load per lane; otherwise four byte loads.
+constexpr uint32_t OFF_OUT = 0x80000000u;
+
 template <bool AL>
 struct LaneRow {
-    const uint8_t *base;
-    int64_t ld;
-    int W, H;
-    uint32_t off;  // this lane's first column (columns < 0 wrap to huge: zero)
+    uint32_t off[AL ? 1 : 4];
 
-    __device__ __forceinline__ LaneRow(const uint8_t *I, int64_t ld_, int cb, int W_, int H_)
-        : base(I), ld(ld_), W(W_), H(H_), off((uint32_t)cb)
+    __device__ __forceinline__ LaneRow(int cb, int W)
     {
+#pragma unroll
+        for (int q = 0; q < (AL ? 1 : 4); ++q)
+            off[q] = (cb + q >= 0 && cb + q < W) ? (uint32_t)(cb + q) : OFF_OUT;
     }
 
-    __device__ __forceinline__ uint32_t operator()(int row) const
+    __device__ __forceinline__ uint32_t load(__amdgpu_buffer_rsrc_t d, uint32_t so) const
     {
-        const bool in = (row >= 0) && (row < H);
-        const __amdgpu_buffer_rsrc_t r =
-            rsrc(base + (int64_t)(in ? row : 0) * ld, in ? (uint32_t)W : 0u);
-        if (AL) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        if (AL) return __builtin_amdgcn_raw_buffer_load_b32(d, (int)off[0], (int)so, 0);
         uint32_t v = 0u;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            v |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)(off + q), 0, 0) << (8 * q);
+            v |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, (int)off[AL ? 0 : q], (int)so, 0) << (8 * q);
         return v;
     }
 };
+
+// Marks v as used here, so the wait for the load that produced it is placed
+// at this point (and nowhere later).
+__device__ __forceinline__ void settle(uint32_t v) { asm volatile("" : : "v"(v)); }
 
 // Add four rows (one dword per row, four columns each) to the column sums:
 // transpose the 4x4 bytes so each dword holds one column, then one SAD (sum)
@@ -185,15 +199,27 @@ __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S
 }
 
 // Guard of the float32 decision: |t32 - t64| <= 2^-18 * mag, where mag bounds
-// the magnitudes of the terms of t (|m| (c1 s + |c0|) for Sauvola,
-// m + |k| s for Niblack).  The rounding-error bound of the float32 sequence is
-// below 20 units of 2^-24 relative to mag; 2^-18 leaves a factor 3 margin.
+// the magnitudes of the terms of t (m (c1 s + |c0|) for Sauvola, m + |k| s for
+// Niblack).  With 1/n correctly rounded, n*S2 - S1^2 exact, a 1-ulp square
+// root and the products below, the float32 sequence stays within 12 units of
+// 2^-24 relative to mag (binary64 rounding included), so 2^-18 leaves a
+// factor 5 margin.
 constexpr float GUARD = 3.814697265625e-06f;  // 2^-18
 
-template <int MODE, bool AL>
+// Input dwords of one row group: entering rows (y + u), leaving rows (y - o)
+// and centre rows (y) of the group's R rows, for this lane's four columns.
+template <int R>
+struct GroupRows {
+    uint32_t a[R], b[R], c[R];
+};
+
+// MS: also write the window mean and standard deviation (always true for
+// MODE_MEANSTD, unused for MODE_SUMS).
+template <int MODE, bool AL, bool MS>
 __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
     constexpr int R = ROWS_PER_GROUP;
+    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
     const int NT = blockDim.x;
     const int PS = prefix_row_words(NT);
     uint32_t *Gray = smem + R * 2 * PS;   // [R][NT] gray levels of the group's rows
@@ -212,7 +238,19 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const int H = a.H, W = a.W, o = a.o, u = a.u;
     // vertical pass: lane owns the four columns cb .. cb+3
     const int cb = xh + COLS_PER_LANE * tid;
-    const LaneRow<AL> ld(a.I, a.ldI, cb, W, H);
+    const LaneRow<AL> ld(cb, W);
+    // The strip reads input rows rlo .. rhi only (its priming rows, then the
+    // entering, leaving and centre rows); one descriptor covers them.  The
+    // planner keeps this span, and the output spans below, under 2^31 bytes.
+    const int rlo = max(y0 - o, 0), rhi = min(y1 - 1 + u, H - 1);
+    const uint32_t ld32 = (uint32_t)a.ldI;
+    const uint8_t *rbase = a.I + (int64_t)rlo * a.ldI;
+    const uint32_t rspan = (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W;
+    const __amdgpu_buffer_rsrc_t rin = rsrc(rbase, rspan);
+    // row `row` if rlo <= row <= rhi (in), else zeros
+    auto row_load = [&](int row, bool in) -> uint32_t {
+        return ld.load(rsrc(rbase, in ? rspan : 0u), in ? (uint32_t)(row - rlo) * ld32 : 0u);
+    };
 
     // zero the left pads (and index 0) of every prefix row once
     for (int i = tid; i < R * 2 * (PREFIX_LPAD + 1); i += NT) {
@@ -224,73 +262,116 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     // but lane t takes columns t, t+64, t+128, t+192 of them, so that the
     // prefix reads of a wavefront hit consecutive LDS words (no bank
     // conflicts) and each store instruction writes 64 consecutive elements.
+    // Lanes whose columns lie outside the tile compute as the others do; the
+    // range checks of the output descriptors drop their stores.
     const int ec0 = xh + 256 * wave + lane;  // column k is ec0 + 64 k
     const int ai0 = PREFIX_LPAD + ec0 + a.r - xh + 1;  // prefix word of j + r
     const int bi0 = PREFIX_LPAD + ec0 - a.l - xh + 1;  // prefix word of j - l
-    int nc[4];
-    float rnc[4];
-    bool valid[4];
+    const uint32_t ow = (uint32_t)(x1 - x0);  // output row width of the tile
+    // Output descriptors cover the strip's rows of the tile (columns x0 ..
+    // x1-1), the row chosen by scalar offset; a lane's element offsets are
+    // 2^31 for columns outside the tile, so those stores are dropped.
+    uint32_t o4[4], o1[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int j = ec0 + 64 * k;
-        valid[k] = (j >= x0) && (j < x1);
-        nc[k] = valid[k] ? min(j + a.r, W - 1) - max(j - a.l, -1) : 1;
-        rnc[k] = 1.0f / (float)nc[k];
+        const int e = ec0 + 64 * k - x0;
+        const bool in = e >= 0 && e < (int)ow;
+        o4[k] = in ? 4u * (uint32_t)e : OFF_OUT;
+        o1[k] = in ? (uint32_t)e : OFF_OUT;
     }
-    const bool any_valid = valid[0] || valid[1] || valid[2] || valid[3];
+    const uint32_t last = (uint32_t)(y1 - 1 - y0);  // strip rows - 1
+    auto out_rsrc = [&](const void *p, int64_t ldo, int es) {
+        return rsrc((const uint8_t *)p + ((int64_t)y0 * ldo + x0) * es,
+                    (uint32_t)es * (last * (uint32_t)ldo + ow));
+    };
+    // (descriptors of outputs this variant does not write are never used)
+    const __amdgpu_buffer_rsrc_t dS1 = out_rsrc(a.S1, a.ldS, 4), dS2 = out_rsrc(a.S2, a.ldS, 4);
+    const __amdgpu_buffer_rsrc_t dM = out_rsrc(a.mean, a.ldMS, 4), dSd = out_rsrc(a.stdv, a.ldMS, 4);
+    const __amdgpu_buffer_rsrc_t dK = out_rsrc(a.mask, a.ldM, 1);
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
     {
         const int p0 = max(y0 - o, 0);
         const int p1 = min(y0 + u - 1, H - 1);
-        int row = p0;
-        // batches of sixteen rows: all sixteen loads in flight, then four
-        // SAD/DOT4 groups
-        for (; row + 15 <= p1; row += 16) {
-            uint32_t v[16];
+        // batches of PB rows: all PB loads in flight, then PB/4 SAD/DOT4
+        // groups (fewer rows per batch where each row takes four byte loads)
+        constexpr int PB = AL ? 32 : 8;
+        int row = p0;  // p0 == rlo
+        for (; row + PB - 1 <= p1; row += PB) {
+            const uint32_t so = (uint32_t)(row - p0) * ld32;
+            uint32_t v[PB];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = ld(row + q);
+            for (int q = 0; q < PB; ++q) v[q] = ld.load(rin, so + (uint32_t)q * ld32);
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < PB / 4; ++g)
                 add4rows(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], C, D);
         }
-        for (; row + 3 <= p1; row += 4) add4rows(ld(row), ld(row + 1), ld(row + 2), ld(row + 3), C, D);
-        for (; row <= p1; ++row) add4rows(ld(row), 0u, 0u, 0u, C, D);
+        if (row <= p1) {  // fewer than PB rows left: rows past p1 count zero
+            uint32_t v[PB];
+#pragma unroll
+            for (int q = 0; q < PB; ++q) v[q] = row_load(row + q, row + q <= p1);
+#pragma unroll
+            for (int g = 0; g < PB / 4; ++g)
+                if (row + 4 * g <= p1) add4rows(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], C, D);
+        }
     }
 
     // ---- march down the strip, R rows per group ----
-    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
-    // next group's entering, leaving and centre-row dwords; the centre rows
-    // go through LDS to reach the epilogue's column assignment
-    uint32_t na[R], nb[R], ni[R];
-    auto load_group = [&](int yg) {
+    // The next group's rows are loaded at the top of an iteration and waited
+    // for just before the iteration's stores: one wait counter tracks loads
+    // and stores in issue order, so a wait at the top of the loop would also
+    // wait for the stores the previous epilogue has just issued.
+    GroupRows<R> X;
+    auto load_group = [&](int yg, GroupRows<R> &g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            na[r] = ld(yg + r + u);
-            nb[r] = ld(yg + r - o);
-            if (need_i) ni[r] = ld(yg + r);
+            const int ra = yg + r + u, rb = yg + r - o;
+            g.a[r] = row_load(ra, ra <= rhi);
+            g.b[r] = row_load(rb, rb >= rlo);
+            if (need_i) g.c[r] = row_load(yg + r, yg + r <= rhi);
         }
     };
-    load_group(y0);
-    const uint8_t *gray_b = (const uint8_t *)Gray;
-    for (int yg = y0; yg < y1; yg += R) {
-        uint32_t va[R], vb[R];
+    auto settle_group = [&](GroupRows<R> &g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            va[r] = na[r];
-            vb[r] = nb[r];
-            if (need_i) Gray[r * NT + tid] = ni[r];
+            settle(g.a[r]);
+            settle(g.b[r]);
+            if (need_i) settle(g.c[r]);
         }
-        if (yg + R < y1) load_group(yg + R);  // prefetch the next group
+    };
+
+    // Epilogue constants.  n = nr * nc changes with the row only near the top
+    // and bottom image borders, so (double) n and 1/n per column are cached
+    // for the current row count nr.
+    int cur_nr = -1;
+    double nd[4] = {0.0, 0.0, 0.0, 0.0};
+    float rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // Guard of the float32 decision (near iff |d| <= GUARD * mag): with
+    // s <= 127.5 for 8-bit data, mag <= m (c1 127.5 + |c0|) for Sauvola and
+    // mag <= m + |k| 127.5 for Niblack, so near iff |d| + gB + gA m <= 0.
+    const float gA = (MODE == MODE_SAUVOLA)
+                         ? -GUARD * __builtin_fmaf(__builtin_fabsf(a.c1), 127.5f, __builtin_fabsf(a.c0))
+                         : -GUARD;
+    const float gB = (MODE == MODE_SAUVOLA) ? 0.0f : -GUARD * (a.kabs * 127.5f);
+    const uint8_t *gray_b = (const uint8_t *)Gray;
+
+    load_group(y0, X);
+    settle_group(X);
+    for (int yg = y0; yg < y1; yg += R) {
+        const GroupRows<R> cur = X;
+        if (yg + R < y1) load_group(yg + R, X);  // prefetch the next group
         // column recurrence and per-lane prefixes for each row of the group
         uint32_t pc[R][4], pd[R][4], sc[R], sd[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            // the centre row's gray levels, for the epilogue's column order
+            // (read back by lanes of this same wavefront only)
+            if (need_i) Gray[r * NT + tid] = cur.c[r];
             if (yg + r < y1) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const int ak = (int)byte_of(va[r], k), bk = (int)byte_of(vb[r], k);
+                    const int ak = (int)byte_of(cur.a[r], k), bk = (int)byte_of(cur.b[r], k);
                     const int dk = ak - bk;
                     C[k] += (uint32_t)dk;
                     D[k] += (uint32_t)(dk * (ak + bk));
@@ -337,11 +418,13 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             }
         }
         __syncthreads();
+        settle_group(X);  // the next group's rows, before this group's stores
 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = yg + r;
-            if (y >= y1 || !any_valid) continue;
+            if (y >= y1) continue;  // past the strip (last group only)
+            const uint32_t dy = (uint32_t)(y - y0);
             const uint32_t *pa = smem + r * 2 * PS + ai0;  // this lane's window ends
             const uint32_t *pb = smem + r * 2 * PS + bi0;
             uint32_t S1[4], S2[4];
@@ -350,26 +433,12 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
                 S1[k] = pa[64 * k] - pb[64 * k];
                 S2[k] = pa[PS + 64 * k] - pb[PS + 64 * k];
             }
-            // gray levels of the lane's four epilogue columns (byte offsets
-            // relative to the tile's first halo'd column)
-            uint32_t vi = 0u;
-            if (need_i) {
-                const uint8_t *gp = gray_b + r * NT * 4 + (ec0 - xh);
-                vi = (uint32_t)gp[0] | ((uint32_t)gp[64] << 8) | ((uint32_t)gp[128] << 16) |
-                     ((uint32_t)gp[192] << 24);
-            }
-
-            // output descriptors cover this tile's columns [x0, x1) of row y;
-            // lanes outside it fall out of range and store nothing
-            const uint32_t ow = (uint32_t)(x1 - x0);
-            const int eo = ec0 - x0;  // negative for left-halo lanes: out of range
             if (MODE == MODE_SUMS) {
-                const __amdgpu_buffer_rsrc_t r1 = rsrc(a.S1 + (int64_t)y * a.ldS + x0, 4 * ow);
-                const __amdgpu_buffer_rsrc_t r2 = rsrc(a.S2 + (int64_t)y * a.ldS + x0, 4 * ow);
+                const uint32_t so = 4u * dy * (uint32_t)a.ldS;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    __builtin_amdgcn_raw_buffer_store_b32(S1[k], r1, 4 * (eo + 64 * k), 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(S2[k], r2, 4 * (eo + 64 * k), 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(S1[k], dS1, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(S2[k], dS2, (int)o4[k], (int)so, STORE_NT);
                 }
                 continue;
             }
@@ -377,76 +446,99 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             // moments: n = nr * nc; n*S2 - S1^2 is formed exactly in binary64
             // (every term is an integer below 2^53)
             const int nr = min(y + u, H - 1) - max(y - o, -1);
-            const float rnr = (nr == a.h) ? a.rh : __builtin_amdgcn_rcpf((float)nr);
+            if (nr != cur_nr) {
+                cur_nr = nr;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int j = ec0 + 64 * k;
+                    const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
+                    nd[k] = (double)max(nr, 1) * (double)nc;
+                    rn[k] = 1.0f / (float)nd[k];
+                }
+            }
             float m[4], s[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float rn = rnr * rnc[k];
-                m[k] = (float)S1[k] * rn;
+                m[k] = (float)S1[k] * rn[k];
                 const double s1d = (double)S1[k];
-                const double nd = (double)(uint32_t)(nr * nc[k]);
-                const double vn = __builtin_fma(nd, (double)S2[k], -(s1d * s1d));
-                s[k] = __builtin_amdgcn_sqrtf((float)vn) * rn;
+                const double vn = __builtin_fma(nd[k], (double)S2[k], -(s1d * s1d));
+                s[k] = __builtin_amdgcn_sqrtf((float)vn) * rn[k];
             }
-            if (a.mean != nullptr) {
-                const __amdgpu_buffer_rsrc_t rm = rsrc(a.mean + (int64_t)y * a.ldMS + x0, 4 * ow);
-                const __amdgpu_buffer_rsrc_t rs = rsrc(a.stdv + (int64_t)y * a.ldMS + x0, 4 * ow);
+            if (MS) {
+                const uint32_t so = 4u * dy * (uint32_t)a.ldMS;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(m[k]), rm, 4 * (eo + 64 * k), 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s[k]), rs, 4 * (eo + 64 * k), 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(m[k]), dM, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s[k]), dSd, (int)o4[k], (int)so, STORE_NT);
                 }
             }
             if (MODE == MODE_MEANSTD) continue;
 
-            // threshold and mask: the sign bit of d = I - t is the mask bit
-            // (I - t rounds to +0 when equal); pixels within the guard are
+            // threshold and mask: the sign bit of d (I - t, exact sign) is the
+            // mask bit (d is +0 when I equals t); pixels within the guard are
             // re-decided with the binary64 sequence (one call site, rare)
-            const __amdgpu_buffer_rsrc_t rk = rsrc(a.mask + (int64_t)y * a.ldM + x0, ow);
+            const uint8_t *gp = gray_b + r * NT * 4 + (ec0 - xh);  // column ec0 + 64 k
+            float gv[4], nm[4];
             uint32_t bits[4];
-            uint32_t near = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                float t, mag;
+                gv[k] = (float)gp[64 * k];
+                float d;
                 if (MODE == MODE_SAUVOLA) {
-                    t = m[k] * __builtin_fmaf(a.c1, s[k], a.c0);
-                    mag = __builtin_fmaf(a.c2, m[k], t);  // m (c1 s + |c0|)
+                    const float q = __builtin_fmaf(a.c1, s[k], a.c0);  // 1 + k (s/R - 1)
+                    d = __builtin_fmaf(-m[k], q, gv[k]);
+                    nm[k] = __builtin_fmaf(gA, m[k], __builtin_fabsf(d));
                 } else {
-                    t = __builtin_fmaf(a.c1, s[k], m[k]);
-                    mag = __builtin_fmaf(a.kabs, s[k], m[k]);
+                    d = gv[k] - __builtin_fmaf(a.c1, s[k], m[k]);
+                    nm[k] = __builtin_fmaf(gA, m[k], __builtin_fabsf(d) + gB);
                 }
-                const float d = (float)byte_of(vi, k) - t;
                 bits[k] = __float_as_uint(d) >> 31;
-                if (valid[k] && (a.force_ref || __builtin_fabsf(d) <= GUARD * mag)) near |= 1u << k;
             }
-            while (near != 0) {
-                const int k = __builtin_ctz(near);
-                near &= near - 1;
-                const uint32_t s1 = (k == 0) ? S1[0] : (k == 1) ? S1[1] : (k == 2) ? S1[2] : S1[3];
-                const uint32_t s2 = (k == 0) ? S2[0] : (k == 1) ? S2[1] : (k == 2) ? S2[2] : S2[3];
-                const int nck = (k == 0) ? nc[0] : (k == 1) ? nc[1] : (k == 2) ? nc[2] : nc[3];
-                const uint32_t iv = byte_of(vi >> (8 * k), 0);
-                const uint32_t bit =
-                    below_reference(iv, s1, s2, (int64_t)nr * nck, MODE, a.k64, a.R64) ? 1u : 0u;
-                bits[0] = (k == 0) ? bit : bits[0];
-                bits[1] = (k == 1) ? bit : bits[1];
-                bits[2] = (k == 2) ? bit : bits[2];
-                bits[3] = (k == 3) ? bit : bits[3];
+            const float nmin = __builtin_fminf(__builtin_fminf(nm[0], nm[1]), __builtin_fminf(nm[2], nm[3]));
+            if (a.force_ref || nmin <= 0.0f) {
+                uint32_t near = a.force_ref ? 0xfu
+                                            : (uint32_t)(nm[0] <= 0.0f) | ((uint32_t)(nm[1] <= 0.0f) << 1) |
+                                                  ((uint32_t)(nm[2] <= 0.0f) << 2) |
+                                                  ((uint32_t)(nm[3] <= 0.0f) << 3);
+                while (near != 0) {
+                    const int k = __builtin_ctz(near);
+                    near &= near - 1;
+                    const uint32_t s1 = (k == 0) ? S1[0] : (k == 1) ? S1[1] : (k == 2) ? S1[2] : S1[3];
+                    const uint32_t s2 = (k == 0) ? S2[0] : (k == 1) ? S2[1] : (k == 2) ? S2[2] : S2[3];
+                    const double n = (k == 0) ? nd[0] : (k == 1) ? nd[1] : (k == 2) ? nd[2] : nd[3];
+                    const float g = (k == 0) ? gv[0] : (k == 1) ? gv[1] : (k == 2) ? gv[2] : gv[3];
+                    const uint32_t bit = below_reference((uint32_t)g, s1, s2, (int64_t)n, MODE,
+                                                         a.k64, a.R64)
+                                             ? 1u
+                                             : 0u;
+                    bits[0] = (k == 0) ? bit : bits[0];
+                    bits[1] = (k == 1) ? bit : bits[1];
+                    bits[2] = (k == 2) ? bit : bits[2];
+                    bits[3] = (k == 3) ? bit : bits[3];
+                }
             }
+            const uint32_t sok = dy * (uint32_t)a.ldM;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[k], rk, eo + 64 * k, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[k], dK, (int)o1[k], (int)sok, STORE_NT);
         }
     }
 }
 
-template <int MODE, bool AL>
+template <int MODE, bool AL, bool MS>
 __global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
 {
     extern __shared__ uint32_t smem[];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = L / a.nsy;
-    box_tile<MODE, AL>(a, tx, L - tx * a.nsy, smem);
+    box_tile<MODE, AL, MS>(a, tx, L - tx * a.nsy, smem);
+}
+
+template <int MODE, bool MS>
+__device__ __forceinline__ void batched_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
+{
+    if (a.aligned) box_tile<MODE, true, MS>(a, tx, sy, smem);
+    else box_tile<MODE, false, MS>(a, tx, sy, smem);
 }
 
 // Persistent grid over the tiles of a ragged batch.  Tiles are numbered in the
@@ -478,12 +570,13 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
         const int local = t - prefix[lo];
         const int tx = local / a.nsy;
         const int sy = local - tx * a.nsy;
+        const bool ms = a.mean != nullptr;
         if (a.mode == MODE_SAUVOLA) {
-            if (a.aligned) box_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
-            else box_tile<MODE_SAUVOLA, false>(a, tx, sy, smem);
+            if (ms) batched_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
+            else batched_tile<MODE_SAUVOLA, false>(a, tx, sy, smem);
         } else {
-            if (a.aligned) box_tile<MODE_NIBLACK, true>(a, tx, sy, smem);
-            else box_tile<MODE_NIBLACK, false>(a, tx, sy, smem);
+            if (ms) batched_tile<MODE_NIBLACK, true>(a, tx, sy, smem);
+            else batched_tile<MODE_NIBLACK, false>(a, tx, sy, smem);
         }
         __syncthreads();  // the tile's LDS is free before the next claim
     }
@@ -497,19 +590,25 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
     }
 }
 
-template <int MODE, bool AL>
-hipError_t launch_mode(const BoxJob &a, hipStream_t stream)
+template <int MODE, bool AL, bool MS>
+hipError_t launch_variant(const BoxJob &a, hipStream_t stream)
 {
     const int NT = a.threads;
     const size_t lds = (size_t)box_lds_words(NT) * sizeof(uint32_t);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_box<MODE, AL>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_box<MODE, AL, MS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int blocks = a.ntx * a.nsy;
-    hipLaunchKernelGGL((k_box<MODE, AL>), dim3(blocks), dim3(NT), lds, stream, a);
+    hipLaunchKernelGGL((k_box<MODE, AL, MS>), dim3(blocks), dim3(NT), lds, stream, a);
     return hipGetLastError();
+}
+
+template <int MODE, bool MS>
+hipError_t launch_mode(const BoxJob &a, hipStream_t stream)
+{
+    return a.aligned ? launch_variant<MODE, true, MS>(a, stream) : launch_variant<MODE, false, MS>(a, stream);
 }
 
 }  // namespace
@@ -560,18 +659,27 @@ void plan_box(BoxJob &a, int strip_override, int threads_override)
         strip = (int)(((long)a.H * a.ntx + target - 1) / target);
         if (strip < 4) strip = 4;
     }
+    // keep the spans of a tile's descriptors (input rows rlo .. rhi, output
+    // rows of the strip) below 2^31 bytes; the entry points guarantee that
+    // one row strip fits
+    const int64_t LIM = ((int64_t)1 << 31) - 1;
+    int64_t cap = (LIM - a.W) / a.ldI - a.h + 1;
+    if (a.S1 != nullptr) cap = std::min(cap, (LIM / 4 - a.W) / a.ldS + 1);
+    if (a.mean != nullptr) cap = std::min(cap, (LIM / 4 - a.W) / a.ldMS + 1);
+    if (a.mask != nullptr) cap = std::min(cap, (LIM - a.W) / a.ldM + 1);
+    if (strip > cap) strip = (int)std::max<int64_t>(cap, 1);
     a.strip = strip;
     a.nsy = (a.H + strip - 1) / strip;
 }
 
 hipError_t launch_box(const BoxJob &a, hipStream_t stream)
 {
-    const bool al = a.aligned != 0;
+    const bool ms = a.mean != nullptr;
     switch (a.mode) {
-    case MODE_SUMS: return al ? launch_mode<MODE_SUMS, true>(a, stream) : launch_mode<MODE_SUMS, false>(a, stream);
-    case MODE_MEANSTD: return al ? launch_mode<MODE_MEANSTD, true>(a, stream) : launch_mode<MODE_MEANSTD, false>(a, stream);
-    case MODE_SAUVOLA: return al ? launch_mode<MODE_SAUVOLA, true>(a, stream) : launch_mode<MODE_SAUVOLA, false>(a, stream);
-    case MODE_NIBLACK: return al ? launch_mode<MODE_NIBLACK, true>(a, stream) : launch_mode<MODE_NIBLACK, false>(a, stream);
+    case MODE_SUMS: return launch_mode<MODE_SUMS, false>(a, stream);
+    case MODE_MEANSTD: return launch_mode<MODE_MEANSTD, true>(a, stream);
+    case MODE_SAUVOLA: return ms ? launch_mode<MODE_SAUVOLA, true>(a, stream) : launch_mode<MODE_SAUVOLA, false>(a, stream);
+    case MODE_NIBLACK: return ms ? launch_mode<MODE_NIBLACK, true>(a, stream) : launch_mode<MODE_NIBLACK, false>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -614,3 +722,4 @@ hipError_t launch_box_batched(void *workspace, hipStream_t stream)
 }
 
 }  // namespace bz
+

@@ -37,10 +37,8 @@ struct BoxJob {
     int64_t ldM;
     // threshold parameters: float fast path and binary64 canonical path
     float c0, c1;          // Sauvola: 1 - k, k / R; Niblack: unused, c1 = k
-    float c2;              // Sauvola: |c0| - c0 (guard magnitude m (c1 s + |c0|) = t + c2 m)
     float kabs;            // |k| (Niblack guard)
     double k64, R64;
-    float rh;              // 1 / h, rounded (interior-row reciprocal)
     int mode;
     // tiling: column tiles of tile_w outputs, row strips of `strip` rows
     int threads;           // block size (multiple of 64, <= 1024)
