@@ -4,7 +4,7 @@ Default workload: Sauvola on a 4096 x 3072 (W x H) uint8 synthetic document,
 h = w = 75, k = 0.5, R = 128, writing the uint8 mask plus float32 window mean
 and standard deviation (10 bytes of algorithmic HBM traffic per pixel).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras] [--pmc]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu] [--pmc]
 
 Prints ONE JSON line.  `value` is Gpix/s over the K timed steps (inputs
 resident in HBM; buffer sets rotated so the 256 MB Infinity Cache cannot serve
@@ -74,6 +74,211 @@ def cpu_baseline(I, h, w, k, R, seconds):
     }
 
 
+def _timeit(fn, n, warm=3):
+    """Median per-call time in microseconds of fn(i) over n calls (HIP events
+    on the current stream around each call)."""
+    import torch
+    for i in range(warm):
+        fn(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for i, (a, b) in enumerate(evs):
+        a.record()
+        fn(i)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e3
+
+
+def _loop_us(fn, n, warm=3):
+    """Average per-call time in microseconds of n back-to-back calls between
+    two events (launch-to-launch throughput)."""
+    import torch
+    for i in range(warm):
+        fn(i)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(n):
+        fn(i)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e3 / n
+
+
+def extras(sets, host, args):
+    """The other measured workloads: window sweep, Niblack, mask-only,
+    mean/std, cache-warm, ragged batch, soft fwd+bwd, quantiles."""
+    import torch
+    import paper_1905_13038_amd as bz
+    from docgen import batch_specs, gen_document, soft_batch
+
+    lib = bz.lib
+    H, W = host.shape
+    px = H * W
+    st = torch.cuda.current_stream().cuda_stream
+    out = {}
+
+    def guarded(name, fn):
+        try:
+            out[name] = fn()
+        except Exception as e:  # report, do not abort the bench line
+            out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+
+    def page_call(method, win, stats, i):
+        img, mask, m, sd = sets[i % len(sets)]
+        mp = m.data_ptr() if stats else None
+        sp = sd.data_ptr() if stats else None
+        if method == "sauvola":
+            rc = lib.bz_sauvola(img.data_ptr(), H, W, W, win, win, 0.5, 128.0, mask.data_ptr(), W,
+                                mp, sp, W, st)
+        else:
+            rc = lib.bz_niblack(img.data_ptr(), H, W, W, win, win, -0.2, mask.data_ptr(), W,
+                                mp, sp, W, st)
+        if rc != 0:
+            raise RuntimeError("status %d" % rc)
+
+    def sweep():
+        res = {}
+        for method in ("sauvola", "niblack"):
+            for win in (15, 32, 75, 151):
+                us = _loop_us(lambda i: page_call(method, win, True, i), 30)
+                res["%s_w%d" % (method, win)] = {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1),
+                                                 "hbm_frac": round(10.0 * px / us / 1e3 / HBM_PEAK_GBS, 4)}
+        g = [v["Gpix_s"] for k, v in res.items() if k.startswith("sauvola")]
+        res["sauvola_min_over_max"] = round(min(g) / max(g), 3)
+        return res
+
+    def mask_only():
+        us = _loop_us(lambda i: page_call("sauvola", 75, False, i), 30)
+        return {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1), "bytes_per_px": 2}
+
+    def mean_std():
+        def f(i):
+            img, mask, m, sd = sets[i % len(sets)]
+            rc = lib.bz_window_mean_std(img.data_ptr(), H, W, W, 75, 75, m.data_ptr(), sd.data_ptr(), W, st)
+            if rc != 0:
+                raise RuntimeError("status %d" % rc)
+        us = _loop_us(f, 30)
+        return {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1), "bytes_per_px": 9}
+
+    def cache_warm():
+        us = _loop_us(lambda i: page_call("sauvola", 75, True, 0), 30)
+        return {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1), "note": "one buffer set, no rotation"}
+
+    def fill_floor():
+        n = (9 * px) // 4
+        bufs = [torch.empty(n, dtype=torch.float32, device=sets[0][0].device) for _ in range(4)]
+        us = _loop_us(lambda i: bufs[i % 4].fill_(1.0), 20)
+        return {"us": round(us, 2), "GB_s": round(4.0 * n / us / 1e3, 1),
+                "note": "torch fill_ of 9 B/px (the output bytes of one page), rotated over 4 buffers"}
+
+    def batch():
+        # 256 ragged pages: crops (at seeded offsets) of one generated 4096 x 4096
+        # page, each copied into its own tensor
+        specs = batch_specs()
+        dev = sets[0][0].device
+        big = torch.from_numpy(gen_document(4096, 4096, 4, noise=10.0, stain=True)).to(dev)
+        rng = np.random.default_rng(4)
+        imgs, params = [], []
+        for d in specs:
+            y = int(rng.integers(0, 4096 - d["H"] + 1))
+            x = int(rng.integers(0, 4096 - d["W"] + 1))
+            imgs.append(big[y:y + d["H"], x:x + d["W"]].clone())
+            params.append({"h": d["h"], "w": d["w"], "k": d["k"], "R": d["R"], "method": "sauvola"})
+        del big
+        tot = sum(int(t.numel()) for t in imgs)
+        plan = bz.BatchPlan(imgs, params)
+        outs = plan.outputs()
+
+        def plain(i):
+            for img, p, (mk, mn, sd) in zip(imgs, params, outs):
+                Hh, Ww = img.shape
+                rc = lib.bz_sauvola(img.data_ptr(), Hh, Ww, Ww, p["h"], p["w"], p["k"], p["R"],
+                                    mk.data_ptr(), Ww, mn.data_ptr(), sd.data_ptr(), Ww, st)
+                if rc != 0:
+                    raise RuntimeError("status %d" % rc)
+        plain_us = _loop_us(plain, 5, warm=1)
+        run_us = _loop_us(lambda i: plan.run(), 10, warm=2)
+        plan.capture()
+        graph_us = _loop_us(lambda i: plan.replay(), 10, warm=2)
+        return {"images": len(imgs), "Gpx": round(tot / 1e9, 4),
+                "graph_replay_us": round(graph_us, 1), "persistent_run_us": round(run_us, 1),
+                "plain_calls_us": round(plain_us, 1),
+                "graph_Gpix_s": round(tot / graph_us / 1e3, 1),
+                "plain_Gpix_s": round(tot / plain_us / 1e3, 1),
+                "graph_hbm_frac": round(10.0 * tot / graph_us / 1e3 / HBM_PEAK_GBS, 4),
+                "inputs": "crops of one seeded 4096x4096 page at seeded offsets, shapes and "
+                          "parameters of the ragged-batch recipe (seed 4)"}
+
+    def soft():
+        B, Hs, Ws, win, tau = 32, 1024, 1024, 32, 2.0
+        I, kk, Wr = soft_batch(B, Hs, Ws)
+        dev = sets[0][0].device
+        I = torch.from_numpy(np.ascontiguousarray(I)).to(dev)
+        kd = torch.from_numpy(np.asarray(kk, dtype=np.float32)).to(dev)
+        Rd = torch.tensor([128.0], dtype=torch.float32, device=dev)
+        gy = torch.from_numpy(np.ascontiguousarray(Wr, dtype=np.float32)).to(dev)
+        y = torch.empty_like(I)
+        gI = torch.empty_like(I)
+        gk = torch.empty_like(kd)
+        gR = torch.empty_like(Rd)
+        nb = int(lib.bz_soft_workspace_size(B, Hs, Ws))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+        def fwd(i):
+            rc = lib.bz_soft_sauvola_fwd(I.data_ptr(), B, Hs, Ws, Ws, win, win, kd.data_ptr(),
+                                         Rd.data_ptr(), tau, y.data_ptr(), st)
+            if rc != 0:
+                raise RuntimeError("status %d" % rc)
+
+        def bwd(i):
+            rc = lib.bz_soft_sauvola_bwd(I.data_ptr(), gy.data_ptr(), B, Hs, Ws, Ws, win, win,
+                                         kd.data_ptr(), Rd.data_ptr(), tau, gI.data_ptr(),
+                                         gk.data_ptr(), gR.data_ptr(), ws.data_ptr(), nb, st)
+            if rc != 0:
+                raise RuntimeError("status %d" % rc)
+        f_us = _loop_us(fwd, 10)
+        b_us = _loop_us(bwd, 10)
+        n = B * Hs * Ws
+        return {"fwd_us": round(f_us, 1), "bwd_us": round(b_us, 1), "fwd_bwd_us": round(f_us + b_us, 1),
+                "fwd_Gpix_s": round(n / f_us / 1e3, 1), "fwd_bwd_Gpix_s": round(n / (f_us + b_us) / 1e3, 1),
+                "fwd_hbm_frac": round(8.0 * n / f_us / 1e3 / HBM_PEAK_GBS, 4),
+                "bwd_hbm_frac": round(12.0 * n / b_us / 1e3 / HBM_PEAK_GBS, 4),
+                "workspace_bytes": nb, "shape": [B, Hs, Ws], "h": win, "tau": tau}
+
+    def quantiles():
+        Hq, Wq = 1536, 2048
+        dev = sets[0][0].device
+        img = torch.from_numpy(gen_document(Hq, Wq, 3, noise=10.0, stain=True)).to(dev)
+        Q = torch.empty_like(img)
+        mk = torch.empty_like(img)
+        res = {}
+        for win in (32, 101):
+            for q in (0.5, 0.1):
+                def f(i):
+                    rc = lib.bz_window_quantile(img.data_ptr(), Hq, Wq, Wq, win, win, q, Q.data_ptr(), Wq,
+                                                mk.data_ptr(), Wq, st)
+                    if rc != 0:
+                        raise RuntimeError("status %d" % rc)
+                us = _loop_us(f, 10)
+                npx = Hq * Wq
+                res["h%d_q%g" % (win, q)] = {"us": round(us, 1), "Gpix_s": round(npx / us / 1e3, 2),
+                                            "G_updates_s": round(2.0 * win * npx / us / 1e3, 1)}
+        return res
+
+    guarded("window_sweep", sweep)
+    guarded("sauvola_w75_mask_only", mask_only)
+    guarded("mean_std_w75", mean_std)
+    guarded("sauvola_w75_cache_warm", cache_warm)
+    guarded("write_floor_9Bpx", fill_floor)
+    guarded("ragged_batch_256", batch)
+    guarded("soft_fwd_bwd_32x1024x1024_h32", soft)
+    guarded("quantile_2048x1536", quantiles)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +287,8 @@ def main():
     ap.add_argument("--sets", type=int, default=8, help="rotated buffer sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (window sweep, batch, soft, quantiles)")
     ap.add_argument("--pmc", action="store_true",
                     help="counter run: 3 launches + 3 plain 1 GiB copies, no JSON")
     ap.add_argument("--win", type=int, default=75)
@@ -171,6 +377,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, win, win, k, R, args.cpu_seconds)
+    if not args.no_extras:
+        out["extras"] = extras(sets, host, args)
     print(json.dumps(out), flush=True)
 
 

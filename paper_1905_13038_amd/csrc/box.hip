@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace bz {
@@ -39,16 +40,26 @@ constexpr int ROWS_PER_GROUP = BZ_ROWS_PER_GROUP;
 // PREFIX_LPAD + i.  The PREFIX_LPAD words below index 0 hold zeros and the
 // PREFIX_RPAD words above index 4 NT repeat the last prefix, so a window that
 // reaches past either end of the tile reads the right value without an index
-// clamp (out-of-image columns contribute zero).  PREFIX_LPAD + 1 is a multiple
-// of 4, so each lane's indices 4t+1 .. 4t+4 form one aligned 16-byte group.
+// clamp (out-of-image columns contribute zero; the epilogue's columns run up
+// to halo + 4 NT - 1, so the right pad covers halo + r <= 256 words).
+// PREFIX_LPAD + 1 is a multiple of 4, so each lane's indices 4t+1 .. 4t+4
+// form one aligned 16-byte group.
 constexpr int PREFIX_LPAD = 131;
-constexpr int PREFIX_RPAD = 128;
+constexpr int PREFIX_RPAD = 256;
 __host__ __device__ constexpr int prefix_row_words(int NT)
 {
     return PREFIX_LPAD + 1 + COLS_PER_LANE * NT + PREFIX_RPAD + 4;
 }
-// After the prefix rows: per group row, the gray levels of the row (one dword
-// per lane, NT words), then the wave totals.
+// LDS of a tile, for the R rows of a group: the prefix rows (S1 and S2 per
+// row), the gray levels of the rows (one dword per lane), and the wave totals.
+// Gray rows: two sets (alternating by group) of R rows of NT words plus 4
+// words that absorb the writes of halo columns.
+__host__ __device__ constexpr int gray_row_words(int NT) { return NT + 4; }
+__host__ __device__ constexpr int box_buffer_words(int NT)
+{
+    return 2 * ROWS_PER_GROUP * prefix_row_words(NT) + 2 * ROWS_PER_GROUP * gray_row_words(NT) +
+           2 * ROWS_PER_GROUP * MAX_WAVES;
+}
 
 // Workgroup b is placed on XCD (b mod 8).  Give every XCD a contiguous range
 // of logical tiles so that the halo rows shared by vertically adjacent strips
@@ -116,11 +127,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_
 // scalar offset so = (row - r0) * ld.  Pixels outside the image read as zero
 // (Section 3.2's convention): a lane's offset is its column, replaced by 2^31
 // where the column lies outside [0, W), and rows outside the image are read
-// through a descriptor of no bytes.  Every valid offset is below W and every
-// invalid one at least 2^31, above any descriptor size used here, so the
-// result does not depend on whether the hardware includes the scalar offset
-// in its range check.  In the aligned form (4-byte aligned rows, W a multiple
-// of 4) one dword load per lane; otherwise four byte loads.
+// through a descriptor of no bytes.  The hardware range check compares the
+// lane offset plus the scalar offset with the descriptor size: valid lanes
+// stay below it and offsets of 2^31 exceed every size used here (spans are
+// kept below 2^31 bytes).  In the aligned form (4-byte aligned rows, W a
+// multiple of 4) one dword load per lane; otherwise four byte loads.
 constexpr uint32_t OFF_OUT = 0x80000000u;
 
 template <bool AL>
@@ -144,6 +155,11 @@ struct LaneRow {
         return v;
     }
 };
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
 
 // Marks v as used here, so the wait for the load that produced it is placed
 // at this point (and nowhere later).
@@ -213,6 +229,18 @@ struct GroupRows {
     uint32_t a[R], b[R], c[R];
 };
 
+// One tile: output columns [x0, x1) of the strip of rows [y0, y1).
+//
+// Rows are processed in groups of R.  Each group goes through three phases
+// separated by workgroup barriers:
+//   A  column recurrence for its rows, per-lane prefixes and wavefront scans
+//      (wave totals to LDS),
+//   B  cross-wave combine: the full row prefixes to LDS,
+//   E  epilogue: window sums from the prefixes, moments, threshold, stores.
+// Each phase is written without branches over its rows, so that the compiler
+// can schedule the rows of a group together (the loads of one row under the
+// arithmetic of the other).
+//
 // MS: also write the window mean and standard deviation (always true for
 // MODE_MEANSTD, unused for MODE_SUMS).
 template <int MODE, bool AL, bool MS>
@@ -222,8 +250,15 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
     const int NT = blockDim.x;
     const int PS = prefix_row_words(NT);
-    uint32_t *Gray = smem + R * 2 * PS;   // [R][NT] gray levels of the group's rows
-    uint32_t *Tot = Gray + R * NT;        // [R][2][MAX_WAVES] wave totals
+    const int BW = box_buffer_words(NT);
+    const int GS = gray_row_words(NT);
+    // prefix row of statistic st (0: S1, 1: S2) for group row r; gray row r
+    // of set g; wave totals of statistic st for row r
+    auto prefix_row = [&](int b, int r, int st) { return smem + b * BW + (2 * r + st) * PS; };
+    auto gray_row = [&](int g, int r) { return smem + 2 * R * PS + (g * R + r) * GS; };
+    auto tot_row = [&](int b, int r, int st) {
+        return smem + b * BW + 2 * R * PS + 2 * R * GS + (2 * r + st) * MAX_WAVES;
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -246,48 +281,74 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const uint32_t ld32 = (uint32_t)a.ldI;
     const uint8_t *rbase = a.I + (int64_t)rlo * a.ldI;
     const uint32_t rspan = (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W;
-    const __amdgpu_buffer_rsrc_t rin = rsrc(rbase, rspan);
     // row `row` if rlo <= row <= rhi (in), else zeros
     auto row_load = [&](int row, bool in) -> uint32_t {
         return ld.load(rsrc(rbase, in ? rspan : 0u), in ? (uint32_t)(row - rlo) * ld32 : 0u);
     };
 
     // zero the left pads (and index 0) of every prefix row once
-    for (int i = tid; i < R * 2 * (PREFIX_LPAD + 1); i += NT) {
-        const int row = i / (PREFIX_LPAD + 1);
+    for (int i = tid; i < 2 * R * (PREFIX_LPAD + 1); i += NT) {
+        const int row = i / (PREFIX_LPAD + 1);  // 0 .. 2R-1
         smem[row * PS + (i - row * (PREFIX_LPAD + 1))] = 0u;
     }
 
-    // Epilogue: wave w covers the same 256 columns as in the vertical pass,
-    // but lane t takes columns t, t+64, t+128, t+192 of them, so that the
-    // prefix reads of a wavefront hit consecutive LDS words (no bank
-    // conflicts) and each store instruction writes 64 consecutive elements.
-    // Lanes whose columns lie outside the tile compute as the others do; the
-    // range checks of the output descriptors drop their stores.
-    const int ec0 = xh + 256 * wave + lane;  // column k is ec0 + 64 k
+    // Epilogue: wave w covers output columns x0 + 256 w .. x0 + 256 w + 255,
+    // lane t taking columns t, t+64, t+128, t+192 of them, so that the prefix
+    // reads of a wavefront hit consecutive LDS words (no bank conflicts) and
+    // each store instruction writes 64 consecutive elements.  Lanes whose
+    // columns lie past the tile compute as the others do; the range checks of
+    // the output descriptors drop their stores.
+    const int eo = 256 * wave + lane;  // column k is x0 + eo + 64 k
+    const int ec0 = x0 + eo;
     const int ai0 = PREFIX_LPAD + ec0 + a.r - xh + 1;  // prefix word of j + r
     const int bi0 = PREFIX_LPAD + ec0 - a.l - xh + 1;  // prefix word of j - l
     const uint32_t ow = (uint32_t)(x1 - x0);  // output row width of the tile
     // Output descriptors cover the strip's rows of the tile (columns x0 ..
-    // x1-1), the row chosen by scalar offset; a lane's element offsets are
-    // 2^31 for columns outside the tile, so those stores are dropped.
+    // x1-1), the row chosen by scalar offset (the range check includes it);
+    // a lane's element offsets are 2^31 for columns outside the tile, so
+    // those stores fail the check.
     uint32_t o4[4], o1[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int e = ec0 + 64 * k - x0;
-        const bool in = e >= 0 && e < (int)ow;
-        o4[k] = in ? 4u * (uint32_t)e : OFF_OUT;
-        o1[k] = in ? (uint32_t)e : OFF_OUT;
+        const bool in = eo + 64 * k < (int)ow;
+        o4[k] = in ? 4u * (uint32_t)(eo + 64 * k) : OFF_OUT;
+        o1[k] = in ? (uint32_t)(eo + 64 * k) : OFF_OUT;
     }
     const uint32_t last = (uint32_t)(y1 - 1 - y0);  // strip rows - 1
-    auto out_rsrc = [&](const void *p, int64_t ldo, int es) {
+    // descriptor of an output over the strip's rows; none for rows past it
+    auto out_rsrc = [&](const void *p, int64_t ldo, int es, bool live) {
         return rsrc((const uint8_t *)p + ((int64_t)y0 * ldo + x0) * es,
-                    (uint32_t)es * (last * (uint32_t)ldo + ow));
+                    live ? (uint32_t)es * (last * (uint32_t)ldo + ow) : 0u);
     };
-    // (descriptors of outputs this variant does not write are never used)
-    const __amdgpu_buffer_rsrc_t dS1 = out_rsrc(a.S1, a.ldS, 4), dS2 = out_rsrc(a.S2, a.ldS, 4);
-    const __amdgpu_buffer_rsrc_t dM = out_rsrc(a.mean, a.ldMS, 4), dSd = out_rsrc(a.stdv, a.ldMS, 4);
-    const __amdgpu_buffer_rsrc_t dK = out_rsrc(a.mask, a.ldM, 1);
+    // The gray levels of a row, transposed for the epilogue: the dword of
+    // epilogue lane t of wave w holds the levels of its four columns (byte
+    // k: column x0 + 256 w + t + 64 k).  Vertical lane t writes its four
+    // bytes (columns xh + 4t + q, q = 0..3, four consecutive epilogue lanes)
+    // at gbyte + 4 q; halo columns left of x0 go to a spare word.
+    int gbyte;
+    {
+        const int e = COLS_PER_LANE * tid - (x0 - xh);  // a multiple of 4
+        gbyte = (e >= 0) ? 4 * (64 * (e >> 8) + (e & 63)) + ((e & 255) >> 6) : 4 * NT;
+    }
+
+    // Window sizes of the epilogue columns for rows whose window lies inside
+    // the image vertically (nr = h), and their reciprocals.
+    double ndh[4];
+    float rnh[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int j = ec0 + 64 * k;
+        const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
+        ndh[k] = (double)a.h * (double)nc;
+        rnh[k] = 1.0f / (float)ndh[k];
+    }
+    // Guard of the float32 decision (near iff |d| <= GUARD * mag): with
+    // s <= 127.5 for 8-bit data, mag <= m (|c1| 127.5 + |c0|) for Sauvola and
+    // mag <= m + |k| 127.5 for Niblack, so near iff |d| + gB + gA m <= 0.
+    const float gA = (MODE == MODE_SAUVOLA)
+                         ? -GUARD * __builtin_fmaf(__builtin_fabsf(a.c1), 127.5f, __builtin_fabsf(a.c0))
+                         : -GUARD;
+    const float gB = (MODE == MODE_SAUVOLA) ? 0.0f : -GUARD * (a.kabs * 127.5f);
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
@@ -295,8 +356,12 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         const int p0 = max(y0 - o, 0);
         const int p1 = min(y0 + u - 1, H - 1);
         // batches of PB rows: all PB loads in flight, then PB/4 SAD/DOT4
-        // groups (fewer rows per batch where each row takes four byte loads)
+        // groups (fewer rows per batch where each row takes four byte loads).
+        // All strips prime at once when the kernel starts, so this phase is
+        // bound by the L2 bandwidth; more loads in flight per wavefront were
+        // measured to be slower.
         constexpr int PB = AL ? 32 : 8;
+        const __amdgpu_buffer_rsrc_t rin = rsrc(rbase, rspan);
         int row = p0;  // p0 == rlo
         for (; row + PB - 1 <= p1; row += PB) {
             const uint32_t so = (uint32_t)(row - p0) * ld32;
@@ -307,7 +372,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             for (int g = 0; g < PB / 4; ++g)
                 add4rows(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], C, D);
         }
-        if (row <= p1) {  // fewer than PB rows left: rows past p1 count zero
+        if (row <= p1) {  // fewer than PB rows left: rows past p1 read zero
             uint32_t v[PB];
 #pragma unroll
             for (int q = 0; q < PB; ++q) v[q] = row_load(row + q, row + q <= p1);
@@ -317,18 +382,19 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         }
     }
 
-    // ---- march down the strip, R rows per group ----
-    // The next group's rows are loaded at the top of an iteration and waited
-    // for just before the iteration's stores: one wait counter tracks loads
-    // and stores in issue order, so a wait at the top of the loop would also
-    // wait for the stores the previous epilogue has just issued.
+    // ---- the row groups ----
+    // The next group's rows are loaded during a group and waited for at its
+    // end: one wait counter tracks loads and stores in issue order, so the
+    // wait is placed after the group's stores rather than before them.
     GroupRows<R> X;
     auto load_group = [&](int yg, GroupRows<R> &g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            // rows past the strip load zeros: the recurrence leaves C, D as they are
             const int ra = yg + r + u, rb = yg + r - o;
-            g.a[r] = row_load(ra, ra <= rhi);
-            g.b[r] = row_load(rb, rb >= rlo);
+            const bool on = yg + r < y1;
+            g.a[r] = row_load(ra, on && ra <= rhi);
+            g.b[r] = row_load(rb, on && rb >= rlo);
             if (need_i) g.c[r] = row_load(yg + r, yg + r <= rhi);
         }
     };
@@ -341,41 +407,26 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         }
     };
 
-    // Epilogue constants.  n = nr * nc changes with the row only near the top
-    // and bottom image borders, so (double) n and 1/n per column are cached
-    // for the current row count nr.
-    int cur_nr = -1;
-    double nd[4] = {0.0, 0.0, 0.0, 0.0};
-    float rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    // Guard of the float32 decision (near iff |d| <= GUARD * mag): with
-    // s <= 127.5 for 8-bit data, mag <= m (c1 127.5 + |c0|) for Sauvola and
-    // mag <= m + |k| 127.5 for Niblack, so near iff |d| + gB + gA m <= 0.
-    const float gA = (MODE == MODE_SAUVOLA)
-                         ? -GUARD * __builtin_fmaf(__builtin_fabsf(a.c1), 127.5f, __builtin_fabsf(a.c0))
-                         : -GUARD;
-    const float gB = (MODE == MODE_SAUVOLA) ? 0.0f : -GUARD * (a.kabs * 127.5f);
-    const uint8_t *gray_b = (const uint8_t *)Gray;
-
-    load_group(y0, X);
-    settle_group(X);
-    for (int yg = y0; yg < y1; yg += R) {
-        const GroupRows<R> cur = X;
-        if (yg + R < y1) load_group(yg + R, X);  // prefetch the next group
-        // column recurrence and per-lane prefixes for each row of the group
-        uint32_t pc[R][4], pd[R][4], sc[R], sd[R];
+    uint32_t pc[R][4], pd[R][4], sc[R], sd[R];
+    // A: column recurrence, per-lane prefixes and wave scans of group rows
+    // yg .. yg+R-1
+    auto phase_A = [&](int gs, const GroupRows<R> &cur) {
+        const int b = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             // the centre row's gray levels, for the epilogue's column order
             // (read back by lanes of this same wavefront only)
-            if (need_i) Gray[r * NT + tid] = cur.c[r];
-            if (yg + r < y1) {
+            if (need_i) {
+                uint8_t *gw = (uint8_t *)gray_row(gs, r) + gbyte;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int ak = (int)byte_of(cur.a[r], k), bk = (int)byte_of(cur.b[r], k);
-                    const int dk = ak - bk;
-                    C[k] += (uint32_t)dk;
-                    D[k] += (uint32_t)(dk * (ak + bk));
-                }
+                for (int q = 0; q < 4; ++q) gw[4 * q] = (uint8_t)byte_of(cur.c[r], q);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int ak = (int)byte_of(cur.a[r], k), bk = (int)byte_of(cur.b[r], k);
+                const int dk = ak - bk;
+                C[k] += (uint32_t)dk;
+                D[k] += (uint32_t)(dk * (ak + bk));
             }
             pc[r][0] = C[0];
             pc[r][1] = pc[r][0] + C[1];
@@ -388,140 +439,205 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             sc[r] = wave_scan(pc[r][3]);
             sd[r] = wave_scan(pd[r][3]);
             if (lane == 63) {
-                Tot[(r * 2) * MAX_WAVES + wave] = sc[r];
-                Tot[(r * 2 + 1) * MAX_WAVES + wave] = sd[r];
+                tot_row(b, r, 0)[wave] = sc[r];
+                tot_row(b, r, 1)[wave] = sd[r];
             }
         }
-        __syncthreads();
+    };
+    // B: offsets of the wave totals, full row prefixes into buffer b.  The
+    // scan over the first 16 lanes gives wave w's offset at lane w-1 and the
+    // tile totals (tc, td) at lane nwaves-1; lanes at or above nwaves never
+    // feed those, so they read any total.  Branch-free, so that it can
+    // interleave with the epilogue.
+    uint32_t tc[R], td[R];
+    auto phase_B = [&](int b) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            uint32_t wc = (lane < nwaves) ? Tot[(r * 2) * MAX_WAVES + lane] : 0u;
-            uint32_t wd = (lane < nwaves) ? Tot[(r * 2 + 1) * MAX_WAVES + lane] : 0u;
-            wc = row_scan16(wc);
-            wd = row_scan16(wd);
-            const uint32_t oc = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wc, wave - 1) : 0u;
-            const uint32_t od = (wave > 0) ? (uint32_t)__builtin_amdgcn_readlane((int)wd, wave - 1) : 0u;
+            const uint32_t wc = row_scan16(tot_row(b, r, 0)[lane & 15]);
+            const uint32_t wd = row_scan16(tot_row(b, r, 1)[lane & 15]);
+            const int wl = max(wave - 1, 0);
+            uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)wc, wl);
+            uint32_t od = (uint32_t)__builtin_amdgcn_readlane((int)wd, wl);
+            oc = (wave > 0) ? oc : 0u;
+            od = (wave > 0) ? od : 0u;
+            tc[r] = (uint32_t)__builtin_amdgcn_readlane((int)wc, nwaves - 1);
+            td[r] = (uint32_t)__builtin_amdgcn_readlane((int)wd, nwaves - 1);
             const uint32_t ec_ = sc[r] - pc[r][3] + oc, ed_ = sd[r] - pd[r][3] + od;
-            uint32_t *prc = smem + r * 2 * PS + PREFIX_LPAD + 1;  // index 1
-            uint32_t *prd = prc + PS;
+            uint32_t *prc = prefix_row(b, r, 0) + PREFIX_LPAD + 1;  // index 1
+            uint32_t *prd = prefix_row(b, r, 1) + PREFIX_LPAD + 1;
             *(uint4 *)(prc + COLS_PER_LANE * tid) =
                 make_uint4(pc[r][0] + ec_, pc[r][1] + ec_, pc[r][2] + ec_, pc[r][3] + ec_);
             *(uint4 *)(prd + COLS_PER_LANE * tid) =
                 make_uint4(pd[r][0] + ed_, pd[r][1] + ed_, pd[r][2] + ed_, pd[r][3] + ed_);
-            if (wave == nwaves - 1) {  // right pad: repeat the tile total
-                const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)wc, nwaves - 1);
-                const uint32_t td = (uint32_t)__builtin_amdgcn_readlane((int)wd, nwaves - 1);
-                prc[COLS_PER_LANE * NT + lane] = tc;
-                prc[COLS_PER_LANE * NT + 64 + lane] = tc;
-                prd[COLS_PER_LANE * NT + lane] = td;
-                prd[COLS_PER_LANE * NT + 64 + lane] = td;
+        }
+    };
+    // right pads of buffer b: repeat the tile totals (last wave)
+    auto pads_B = [&](int b) {
+        if (wave == nwaves - 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uint32_t *prc = prefix_row(b, r, 0) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
+                uint32_t *prd = prefix_row(b, r, 1) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
+#pragma unroll
+                for (int q = 0; q < PREFIX_RPAD / 64; ++q) {
+                    prc[64 * q + lane] = tc[r];
+                    prd[64 * q + lane] = td[r];
+                }
             }
         }
-        __syncthreads();
-        settle_group(X);  // the next group's rows, before this group's stores
+    };
 
+    // Statistics of epilogue column k of group row r from buffer b: window
+    // sums, then n = nr * nc and the moments; n*S2 - S1^2 is formed exactly
+    // in binary64 (every term is an integer below 2^53).
+    struct ColStats {
+        uint32_t S1, S2;
+        double n;
+        float m, s;
+    };
+    auto col_stats = [&](int b, int r, int k, int y, bool interior) -> ColStats {
+        ColStats c;
+        const uint32_t *pa = prefix_row(b, r, 0) + ai0 + 64 * k;
+        const uint32_t *pb = prefix_row(b, r, 0) + bi0 + 64 * k;
+        c.S1 = pa[0] - pb[0];
+        c.S2 = pa[PS] - pb[PS];
+        float rn;
+        if (interior) {
+            c.n = (k == 0) ? ndh[0] : (k == 1) ? ndh[1] : (k == 2) ? ndh[2] : ndh[3];
+            rn = (k == 0) ? rnh[0] : (k == 1) ? rnh[1] : (k == 2) ? rnh[2] : rnh[3];
+        } else {
+            const int nr = max(min(y + u, H - 1) - max(y - o, -1), 1);
+            const int j = ec0 + 64 * k;
+            const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
+            c.n = (double)nr * (double)nc;
+            rn = 1.0f / (float)c.n;
+        }
+        c.m = (float)c.S1 * rn;
+        const double s1d = (double)c.S1;
+        const double vn = __builtin_fma(c.n, (double)c.S2, -(s1d * s1d));
+        c.s = __builtin_amdgcn_sqrtf((float)vn) * rn;
+        return c;
+    };
+    // float32 decision: d = I - t with the exact sign of I - t (the mask bit
+    // is its sign bit; d is +0 when I equals t) and the guard metric nm
+    // (the pixel is near the threshold when nm <= 0)
+    auto decide = [&](const ColStats &c, float gv, float &d, float &nm) {
+        if (MODE == MODE_SAUVOLA) {
+            const float q = __builtin_fmaf(a.c1, c.s, a.c0);  // 1 + k (s/R - 1)
+            d = __builtin_fmaf(-c.m, q, gv);
+            nm = __builtin_fmaf(gA, c.m, __builtin_fabsf(d));
+        } else {
+            d = gv - __builtin_fmaf(a.c1, c.s, c.m);
+            nm = __builtin_fmaf(gA, c.m, __builtin_fabsf(d) + gB);
+        }
+    };
+
+    // E: epilogue of the group whose rows start at yg, from buffer b and
+    // gray set gs
+    auto phase_E = [&](int yg, int b, int gs, auto interior_tag) {
+        constexpr bool interior = decltype(interior_tag)::value;
+        uint32_t bits[R][4];
+        float nmin = 1.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = yg + r;
-            if (y >= y1) continue;  // past the strip (last group only)
+            const bool live = y < y1;  // rows past the strip store nothing
             const uint32_t dy = (uint32_t)(y - y0);
-            const uint32_t *pa = smem + r * 2 * PS + ai0;  // this lane's window ends
-            const uint32_t *pb = smem + r * 2 * PS + bi0;
-            uint32_t S1[4], S2[4];
+            ColStats c[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                S1[k] = pa[64 * k] - pb[64 * k];
-                S2[k] = pa[PS + 64 * k] - pb[PS + 64 * k];
-            }
+            for (int k = 0; k < 4; ++k) c[k] = col_stats(b, r, k, y, interior);
             if (MODE == MODE_SUMS) {
                 const uint32_t so = 4u * dy * (uint32_t)a.ldS;
+                const __amdgpu_buffer_rsrc_t d1 = out_rsrc(a.S1, a.ldS, 4, live);
+                const __amdgpu_buffer_rsrc_t d2 = out_rsrc(a.S2, a.ldS, 4, live);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    __builtin_amdgcn_raw_buffer_store_b32(S1[k], dS1, (int)o4[k], (int)so, STORE_NT);
-                    __builtin_amdgcn_raw_buffer_store_b32(S2[k], dS2, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(c[k].S1, d1, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(c[k].S2, d2, (int)o4[k], (int)so, STORE_NT);
                 }
                 continue;
             }
-
-            // moments: n = nr * nc; n*S2 - S1^2 is formed exactly in binary64
-            // (every term is an integer below 2^53)
-            const int nr = min(y + u, H - 1) - max(y - o, -1);
-            if (nr != cur_nr) {
-                cur_nr = nr;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int j = ec0 + 64 * k;
-                    const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
-                    nd[k] = (double)max(nr, 1) * (double)nc;
-                    rn[k] = 1.0f / (float)nd[k];
-                }
-            }
-            float m[4], s[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                m[k] = (float)S1[k] * rn[k];
-                const double s1d = (double)S1[k];
-                const double vn = __builtin_fma(nd[k], (double)S2[k], -(s1d * s1d));
-                s[k] = __builtin_amdgcn_sqrtf((float)vn) * rn[k];
-            }
             if (MS) {
                 const uint32_t so = 4u * dy * (uint32_t)a.ldMS;
+                const __amdgpu_buffer_rsrc_t dm = out_rsrc(a.mean, a.ldMS, 4, live);
+                const __amdgpu_buffer_rsrc_t ds = out_rsrc(a.stdv, a.ldMS, 4, live);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(m[k]), dM, (int)o4[k], (int)so, STORE_NT);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s[k]), dSd, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c[k].m), dm, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c[k].s), ds, (int)o4[k], (int)so, STORE_NT);
                 }
             }
             if (MODE == MODE_MEANSTD) continue;
-
-            // threshold and mask: the sign bit of d (I - t, exact sign) is the
-            // mask bit (d is +0 when I equals t); pixels within the guard are
-            // re-decided with the binary64 sequence (one call site, rare)
-            const uint8_t *gp = gray_b + r * NT * 4 + (ec0 - xh);  // column ec0 + 64 k
-            float gv[4], nm[4];
-            uint32_t bits[4];
+            const uint32_t gw = gray_row(gs, r)[tid];  // byte k: column ec0 + 64 k (this lane's word)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                gv[k] = (float)gp[64 * k];
-                float d;
-                if (MODE == MODE_SAUVOLA) {
-                    const float q = __builtin_fmaf(a.c1, s[k], a.c0);  // 1 + k (s/R - 1)
-                    d = __builtin_fmaf(-m[k], q, gv[k]);
-                    nm[k] = __builtin_fmaf(gA, m[k], __builtin_fabsf(d));
-                } else {
-                    d = gv[k] - __builtin_fmaf(a.c1, s[k], m[k]);
-                    nm[k] = __builtin_fmaf(gA, m[k], __builtin_fabsf(d) + gB);
-                }
-                bits[k] = __float_as_uint(d) >> 31;
+                float d, nm;
+                decide(c[k], (float)byte_of(gw, k), d, nm);
+                bits[r][k] = __float_as_uint(d) >> 31;
+                nmin = __builtin_fminf(nmin, nm);
             }
-            const float nmin = __builtin_fminf(__builtin_fminf(nm[0], nm[1]), __builtin_fminf(nm[2], nm[3]));
-            if (a.force_ref || nmin <= 0.0f) {
-                uint32_t near = a.force_ref ? 0xfu
-                                            : (uint32_t)(nm[0] <= 0.0f) | ((uint32_t)(nm[1] <= 0.0f) << 1) |
-                                                  ((uint32_t)(nm[2] <= 0.0f) << 2) |
-                                                  ((uint32_t)(nm[3] <= 0.0f) << 3);
-                while (near != 0) {
-                    const int k = __builtin_ctz(near);
-                    near &= near - 1;
-                    const uint32_t s1 = (k == 0) ? S1[0] : (k == 1) ? S1[1] : (k == 2) ? S1[2] : S1[3];
-                    const uint32_t s2 = (k == 0) ? S2[0] : (k == 1) ? S2[1] : (k == 2) ? S2[2] : S2[3];
-                    const double n = (k == 0) ? nd[0] : (k == 1) ? nd[1] : (k == 2) ? nd[2] : nd[3];
-                    const float g = (k == 0) ? gv[0] : (k == 1) ? gv[1] : (k == 2) ? gv[2] : gv[3];
-                    const uint32_t bit = below_reference((uint32_t)g, s1, s2, (int64_t)n, MODE,
-                                                         a.k64, a.R64)
-                                             ? 1u
-                                             : 0u;
-                    bits[0] = (k == 0) ? bit : bits[0];
-                    bits[1] = (k == 1) ? bit : bits[1];
-                    bits[2] = (k == 2) ? bit : bits[2];
-                    bits[3] = (k == 3) ? bit : bits[3];
+        }
+        if (!need_i) return;
+        // pixels within the guard: re-decided with the binary64 sequence
+        // (rare; statistics recomputed from LDS, one call site)
+        if (a.force_ref || nmin <= 0.0f) {
+            uint32_t near = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t gw = gray_row(gs, r)[tid];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float d, nm;
+                    decide(col_stats(b, r, k, yg + r, interior), (float)byte_of(gw, k), d, nm);
+                    if (a.force_ref || nm <= 0.0f) near |= 1u << (4 * r + k);
                 }
             }
-            const uint32_t sok = dy * (uint32_t)a.ldM;
+            while (near != 0) {
+                const int i = __builtin_ctz(near);
+                near &= near - 1;
+                const int r = i >> 2, k = i & 3;
+                const ColStats c = col_stats(b, r, k, yg + r, false);
+                const uint32_t gv = ((const uint8_t *)gray_row(gs, r))[4 * tid + k];
+                const uint32_t bit =
+                    below_reference(gv, c.S1, c.S2, (int64_t)c.n, MODE, a.k64, a.R64) ? 1u : 0u;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) bits[rr][kk] = (i == 4 * rr + kk) ? bit : bits[rr][kk];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yg + r;
+            // (after the divergent branch above: scalar values restated as
+            // uniform so the stores take them from scalar registers)
+            const __amdgpu_buffer_rsrc_t dk = out_rsrc(a.mask, a.ldM, 1, y < y1);
+            const uint32_t so = uniform((uint32_t)(y - y0) * (uint32_t)a.ldM);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[k], dK, (int)o1[k], (int)sok, STORE_NT);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[r][k], dk, (int)o1[k], (int)so, STORE_NT);
         }
+    };
+
+    // ---- the groups of the strip ----
+    load_group(y0, X);
+    settle_group(X);
+    int gs = 0;  // gray set of the group (alternates: a wave may still read
+                 // the previous group's set while another writes the next)
+    for (int yg = y0; yg < y1; yg += R, gs ^= 1) {
+        const GroupRows<R> cur = X;
+        if (yg + R < y1) load_group(yg + R, X);  // prefetch the next group
+        phase_A(gs, cur);
+        __syncthreads();
+        phase_B(0);
+        pads_B(0);
+        __syncthreads();
+        settle_group(X);  // the next group's rows, before this group's stores
+        // rows whose windows lie vertically inside the image use the cached
+        // window sizes
+        const bool interior = (yg - o >= -1) && (yg + R - 1 + u <= H - 1);
+        if (interior) phase_E(yg, 0, gs, std::true_type{});
+        else phase_E(yg, 0, gs, std::false_type{});
     }
 }
 
@@ -615,7 +731,7 @@ hipError_t launch_mode(const BoxJob &a, hipStream_t stream)
 
 int box_lds_words(int NT)
 {
-    return ROWS_PER_GROUP * (2 * prefix_row_words(NT) + NT + 2 * MAX_WAVES);
+    return box_buffer_words(NT);
 }
 
 void plan_box(BoxJob &a, int strip_override, int threads_override)
@@ -722,4 +838,3 @@ hipError_t launch_box_batched(void *workspace, hipStream_t stream)
 }
 
 }  // namespace bz
-
