@@ -145,13 +145,17 @@ bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace,
  * (for example inside a captured HIP graph).  bz_batched_plan validates the
  * items, picks each image's tiling (strip_rows: optional HOST array of `count`
  * strip heights in rows, e.g. from an autotuner; NULL or entries < 1 select
- * the default), orders the tiles largest-first, uploads the descriptors into
- * `workspace` and SYNCHRONISES `stream` before returning (it is a set-up call,
- * not part of the hot path).  bz_batched_run launches the single persistent
- * kernel over a planned workspace and returns at once; it neither copies nor
- * synchronises, so it can be captured in a graph and replayed.  The kernel
- * leaves the workspace ready for the next run.  Runs of one workspace must not
- * overlap in time.
+ * the default of 2h rows, at least 32 and at most 128), orders the tiles
+ * largest-first, uploads the descriptors into `workspace` and SYNCHRONISES
+ * `stream` before returning (it is a set-up call, not part of the hot path).
+ * It also records, for this workspace address, which kernel runs it: a batch
+ * whose items all share the method, the 4-byte alignment of image rows and
+ * the presence of mean/std outputs runs a kernel specialised to that choice;
+ * a mixed batch runs the general kernel.  bz_batched_run launches the single
+ * persistent kernel over a planned workspace and returns at once; it neither
+ * copies nor synchronises, so it can be captured in a graph and replayed.  The
+ * kernel leaves the workspace ready for the next run.  Runs of one workspace
+ * must not overlap in time.
  */
 bz_status bz_batched_plan(const bz_item *items, int count, const int *strip_rows,
                           void *workspace, size_t ws_bytes, bz_stream stream);

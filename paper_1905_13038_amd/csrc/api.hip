@@ -324,6 +324,7 @@ bz_status bz_batched_plan(const bz_item *items, int count, const int *strip_rows
         if (total > (int64_t)1 << 30) return BZ_ERR_RANGE;
     }
     prefix[count] = (int)total;
+    register_batch_variant(workspace, batch_variant(dj, count));
     if (inject_launch_fault()) return BZ_ERR_HIP;
     hipError_t e = hipMemcpyAsync(workspace, blob.data(), blob.size(), hipMemcpyHostToDevice,
                                   (hipStream_t)stream);

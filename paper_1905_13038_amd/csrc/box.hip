@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 namespace bz {
@@ -214,12 +215,14 @@ __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S
     return (double)I < t;
 }
 
-// Guard of the float32 decision: |t32 - t64| <= 2^-18 * mag, where mag bounds
-// the magnitudes of the terms of t (m (c1 s + |c0|) for Sauvola, m + |k| s for
-// Niblack).  With 1/n correctly rounded, n*S2 - S1^2 exact, a 1-ulp square
+// Guard of the float32 decision: |t32 - t64| < 2^-18 * mag, where mag bounds
+// the magnitudes of the terms of t (m (|c1| s + |c0|) for Sauvola, m + |k| s
+// for Niblack).  With 1/n correctly rounded, n*S2 - S1^2 exact, a 1-ulp square
 // root and the products below, the float32 sequence stays within 12 units of
 // 2^-24 relative to mag (binary64 rounding included), so 2^-18 leaves a
-// factor 5 margin.
+// factor 5 margin: where |d| >= 2^-18 mag the float32 sign is the binary64
+// one.  A window of zeros (mag = 0, as for columns past the image) is
+// decided exactly.
 constexpr float GUARD = 3.814697265625e-06f;  // 2^-18
 
 // Input dwords of one row group: entering rows (y + u), leaving rows (y - o)
@@ -342,13 +345,13 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         ndh[k] = (double)a.h * (double)nc;
         rnh[k] = 1.0f / (float)ndh[k];
     }
-    // Guard of the float32 decision (near iff |d| <= GUARD * mag): with
-    // s <= 127.5 for 8-bit data, mag <= m (|c1| 127.5 + |c0|) for Sauvola and
-    // mag <= m + |k| 127.5 for Niblack, so near iff |d| + gB + gA m <= 0.
+    // Guard of the float32 decision, near iff |d| < GUARD * mag'.  Sauvola:
+    // s <= 127.5 for 8-bit data bounds mag by m (|c1| 127.5 + |c0|) = m MQ,
+    // so near iff |d| + gA m < 0 with gA = -GUARD MQ.  Niblack: the exact
+    // mag = m + |k| s.
     const float gA = (MODE == MODE_SAUVOLA)
                          ? -GUARD * __builtin_fmaf(__builtin_fabsf(a.c1), 127.5f, __builtin_fabsf(a.c0))
                          : -GUARD;
-    const float gB = (MODE == MODE_SAUVOLA) ? 0.0f : -GUARD * (a.kabs * 127.5f);
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
@@ -520,7 +523,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     };
     // float32 decision: d = I - t with the exact sign of I - t (the mask bit
     // is its sign bit; d is +0 when I equals t) and the guard metric nm
-    // (the pixel is near the threshold when nm <= 0)
+    // (the pixel is near the threshold when nm < 0)
     auto decide = [&](const ColStats &c, float gv, float &d, float &nm) {
         if (MODE == MODE_SAUVOLA) {
             const float q = __builtin_fmaf(a.c1, c.s, a.c0);  // 1 + k (s/R - 1)
@@ -528,7 +531,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             nm = __builtin_fmaf(gA, c.m, __builtin_fabsf(d));
         } else {
             d = gv - __builtin_fmaf(a.c1, c.s, c.m);
-            nm = __builtin_fmaf(gA, c.m, __builtin_fabsf(d) + gB);
+            nm = __builtin_fmaf(gA, __builtin_fmaf(a.kabs, c.s, c.m), __builtin_fabsf(d));
         }
     };
 
@@ -580,7 +583,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         if (!need_i) return;
         // pixels within the guard: re-decided with the binary64 sequence
         // (rare; statistics recomputed from LDS, one call site)
-        if (a.force_ref || nmin <= 0.0f) {
+        if (a.force_ref || nmin < 0.0f) {
             uint32_t near = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -589,7 +592,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
                 for (int k = 0; k < 4; ++k) {
                     float d, nm;
                     decide(col_stats(b, r, k, yg + r, interior), (float)byte_of(gw, k), d, nm);
-                    if (a.force_ref || nm <= 0.0f) near |= 1u << (4 * r + k);
+                    if (a.force_ref || nm < 0.0f) near |= 1u << (4 * r + k);
                 }
             }
             while (near != 0) {
@@ -641,7 +644,10 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     }
 }
 
-template <int MODE, bool AL, bool MS>
+// BIG: the instantiation launched with more than 64 KB of LDS.  It is a
+// separate kernel so that raising its dynamic-LDS limit leaves the LDS
+// reservation, and with it the occupancy, of smaller launches untouched.
+template <int MODE, bool AL, bool MS, bool BIG>
 __global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
 {
     extern __shared__ uint32_t smem[];
@@ -661,10 +667,10 @@ __device__ __forceinline__ void batched_tile(const BoxJob &a, int tx, int sy, ui
 // order of the job array (largest per-tile work first); prefix[i] is the first
 // tile of job i and prefix[count] the total.  The last workgroup to finish
 // resets the counters, so the next launch (or graph replay) starts from zero
-// without a memset.
-__global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
+// without a memset.  `tile(a, tx, sy)` processes one tile of job a.
+template <typename TileFn>
+__device__ __forceinline__ void batched_loop(BatchHeader *hdr, TileFn tile)
 {
-    extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
     const int count = hdr->count;
     const BoxJob *jobs = (const BoxJob *)(hdr + 1);
@@ -685,15 +691,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
         const BoxJob &a = jobs[lo];
         const int local = t - prefix[lo];
         const int tx = local / a.nsy;
-        const int sy = local - tx * a.nsy;
-        const bool ms = a.mean != nullptr;
-        if (a.mode == MODE_SAUVOLA) {
-            if (ms) batched_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
-            else batched_tile<MODE_SAUVOLA, false>(a, tx, sy, smem);
-        } else {
-            if (ms) batched_tile<MODE_NIBLACK, true>(a, tx, sy, smem);
-            else batched_tile<MODE_NIBLACK, false>(a, tx, sy, smem);
-        }
+        tile(a, tx, local - tx * a.nsy);
         __syncthreads();  // the tile's LDS is free before the next claim
     }
     if (threadIdx.x == 0) {
@@ -706,18 +704,61 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
     }
 }
 
+// Any mix of Sauvola/Niblack, alignment and mean/std outputs.
+__global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
+{
+    extern __shared__ uint32_t smem[];
+    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) {
+        const bool ms = a.mean != nullptr;
+        if (a.mode == MODE_SAUVOLA) {
+            if (ms) batched_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
+            else batched_tile<MODE_SAUVOLA, false>(a, tx, sy, smem);
+        } else {
+            if (ms) batched_tile<MODE_NIBLACK, true>(a, tx, sy, smem);
+            else batched_tile<MODE_NIBLACK, false>(a, tx, sy, smem);
+        }
+    });
+}
+
+// Batches whose jobs all share one variant (mode, alignment, mean/std
+// outputs): one tile body, and registers for four waves per SIMD.
+template <int MODE, bool AL, bool MS>
+__global__ __launch_bounds__(BATCH_THREADS, 4) void k_box_batched_v(BatchHeader *hdr)
+{
+    extern __shared__ uint32_t smem[];
+    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) { box_tile<MODE, AL, MS>(a, tx, sy, smem); });
+}
+
+// Kernel of batch variant v (-1: mixed batch).
+const void *batch_kernel(int v)
+{
+    switch (v) {
+    case 0: return (const void *)k_box_batched_v<MODE_SAUVOLA, false, false>;
+    case 1: return (const void *)k_box_batched_v<MODE_SAUVOLA, false, true>;
+    case 2: return (const void *)k_box_batched_v<MODE_SAUVOLA, true, false>;
+    case 3: return (const void *)k_box_batched_v<MODE_SAUVOLA, true, true>;
+    case 4: return (const void *)k_box_batched_v<MODE_NIBLACK, false, false>;
+    case 5: return (const void *)k_box_batched_v<MODE_NIBLACK, false, true>;
+    case 6: return (const void *)k_box_batched_v<MODE_NIBLACK, true, false>;
+    case 7: return (const void *)k_box_batched_v<MODE_NIBLACK, true, true>;
+    default: return (const void *)k_box_batched;
+    }
+}
+
 template <int MODE, bool AL, bool MS>
 hipError_t launch_variant(const BoxJob &a, hipStream_t stream)
 {
     const int NT = a.threads;
     const size_t lds = (size_t)box_lds_words(NT) * sizeof(uint32_t);
+    const int blocks = a.ntx * a.nsy;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_box<MODE, AL, MS>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_box<MODE, AL, MS, true>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_box<MODE, AL, MS, true>), dim3(blocks), dim3(NT), lds, stream, a);
+    } else {
+        hipLaunchKernelGGL((k_box<MODE, AL, MS, false>), dim3(blocks), dim3(NT), lds, stream, a);
     }
-    const int blocks = a.ntx * a.nsy;
-    hipLaunchKernelGGL((k_box<MODE, AL, MS>), dim3(blocks), dim3(NT), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -771,9 +812,12 @@ void plan_box(BoxJob &a, int strip_override, int threads_override)
         int per_cu = 16 / waves;
         if (per_cu < 1) per_cu = 1;
         if (per_cu > 8) per_cu = 8;
+        // one resident round of workgroups: at most `target` tiles (a tile
+        // more would run in a second round and double the time)
         const long target = 256L * per_cu;
         strip = (int)(((long)a.H * a.ntx + target - 1) / target);
         if (strip < 4) strip = 4;
+        while ((long)a.ntx * ((a.H + strip - 1) / strip) > target) ++strip;
     }
     // keep the spans of a tile's descriptors (input rows rlo .. rhi, output
     // rows of the strip) below 2^31 bytes; the entry points guarantee that
@@ -806,35 +850,65 @@ size_t batch_workspace_bytes(int count)
     return (raw + 255) & ~(size_t)255;
 }
 
-int batch_grid()
+int batch_variant(const BoxJob *jobs, int count)
 {
-    static std::mutex mu;
-    static std::vector<int> cache;
+    int v = -2;
+    for (int i = 0; i < count; ++i) {
+        const BoxJob &j = jobs[i];
+        const int vi = (j.mode == MODE_NIBLACK ? 4 : 0) + (j.aligned ? 2 : 0) + (j.mean != nullptr ? 1 : 0);
+        if (v == -2) v = vi;
+        else if (v != vi) return -1;
+    }
+    return v < 0 ? -1 : v;
+}
+
+namespace {
+std::mutex g_batch_mu;
+// kernel variant of each planned workspace (host side)
+std::unordered_map<const void *, int> g_batch_variant;
+// persistent grid size per device and variant
+std::unordered_map<int64_t, int> g_batch_grid;
+}  // namespace
+
+void register_batch_variant(const void *workspace, int variant)
+{
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    g_batch_variant[workspace] = variant;
+}
+
+int batch_grid(int variant)
+{
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
-    std::lock_guard<std::mutex> lock(mu);
-    if ((int)cache.size() <= device) cache.resize(device + 1, 0);
-    if (cache[device] == 0) {
-        int cus = 0, per_cu = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-        const size_t lds = (size_t)box_lds_words(BATCH_THREADS) * sizeof(uint32_t);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_box_batched, BATCH_THREADS, lds) !=
-                hipSuccess ||
-            per_cu <= 0)
-            per_cu = 1;
-        cache[device] = cus * per_cu;
-    }
-    return cache[device];
+    const int64_t key = (int64_t)device * 16 + (variant + 1);
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    auto it = g_batch_grid.find(key);
+    if (it != g_batch_grid.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    const size_t lds = (size_t)box_lds_words(BATCH_THREADS) * sizeof(uint32_t);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(variant), BATCH_THREADS, lds) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    g_batch_grid[key] = cus * per_cu;
+    return cus * per_cu;
 }
 
 hipError_t launch_box_batched(void *workspace, hipStream_t stream)
 {
+    int variant = -1;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mu);
+        auto it = g_batch_variant.find(workspace);
+        if (it != g_batch_variant.end()) variant = it->second;
+    }
     const size_t lds = (size_t)box_lds_words(BATCH_THREADS) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_box_batched, dim3(batch_grid()), dim3(BATCH_THREADS), lds, stream,
-                       (BatchHeader *)workspace);
-    return hipGetLastError();
+    BatchHeader *hdr = (BatchHeader *)workspace;
+    void *args[] = {&hdr};
+    return hipLaunchKernel(batch_kernel(variant), dim3(batch_grid(variant)), dim3(BATCH_THREADS), args, lds,
+                           stream);
 }
 
 }  // namespace bz

@@ -70,8 +70,14 @@ struct alignas(64) BatchHeader {
     int pad[13];
 };
 size_t batch_workspace_bytes(int count);
+// Kernel variant shared by all jobs (0..7: Niblack*4 + aligned*2 + mean/std),
+// or -1 for a mixed batch.
+int batch_variant(const BoxJob *jobs, int count);
+// Remember the variant of a planned workspace; the launch picks the kernel
+// from it (a workspace never registered runs the mixed-batch kernel).
+void register_batch_variant(const void *workspace, int variant);
 hipError_t launch_box_batched(void *workspace, hipStream_t stream);
-int batch_grid();
+int batch_grid(int variant);
 
 // Windowed quantile (Section 3.4).
 struct QuantJob {

@@ -1,0 +1,29 @@
+"""Host logic of the batch strip autotuner (no device needed)."""
+import pytest
+
+from paper_1905_13038_amd import tune
+
+
+def test_window_classes_cover_every_window():
+    assert tune.window_class(1) == tune.WINDOW_CLASSES[0]
+    for lo, hi in zip((0,) + tune.WINDOW_CLASSES[:-1], tune.WINDOW_CLASSES):
+        assert tune.window_class(lo + 1) == hi
+        assert tune.window_class(hi) == hi
+    assert tune.window_class(10 ** 6) == tune.WINDOW_CLASSES[-1]
+
+
+@pytest.mark.parametrize("h,expect", [(1, 32), (11, 32), (16, 32), (17, 34), (51, 102), (64, 128),
+                                      (65, 128), (257, 128)])
+def test_default_strip_is_twice_the_window_within_bounds(h, expect):
+    # the rule the library applies when no strip is given (bz_batched_plan)
+    assert tune.default_strip(h) == expect
+
+
+def test_strips_for_table_and_defaults():
+    params = [{"h": 11}, {"h": 31}, {"h": 75}, {"h": 201}]
+    assert tune.strips_for(params) == [tune.default_strip(p["h"]) for p in params]
+    table = {15: 24, "63": 48}
+    got = tune.strips_for(params, table)
+    assert got == [24, tune.default_strip(31), tune.default_strip(75), tune.default_strip(201)]
+    table2 = {c: 40 for c in tune.WINDOW_CLASSES}
+    assert tune.strips_for(params, table2) == [40, 40, 40, 40]
