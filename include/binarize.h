@@ -149,9 +149,10 @@ bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace,
  * largest-first, uploads the descriptors into `workspace` and SYNCHRONISES
  * `stream` before returning (it is a set-up call, not part of the hot path).
  * It also records, for this workspace address, which kernel runs it: a batch
- * whose items all share the method, the 4-byte alignment of image rows and
- * the presence of mean/std outputs runs a kernel specialised to that choice;
- * a mixed batch runs the general kernel.  bz_batched_run launches the single
+ * whose items all share the method and the presence of mean/std outputs runs
+ * a kernel specialised to that choice (and to 4-byte aligned rows when every
+ * item has them); a batch that mixes methods or outputs runs the general
+ * kernel.  bz_batched_run launches the single
  * persistent kernel over a planned workspace and returns at once; it neither
  * copies nor synchronises, so it can be captured in a graph and replayed.  The
  * kernel leaves the workspace ready for the next run.  Runs of one workspace

@@ -123,37 +123,49 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_
                                              RSRC_FLAGS);
 }
 
-// Reads the four pixels of a lane (columns cb .. cb+3) of one row through a
-// descriptor d over whole rows from a first row r0, the row chosen by the
-// scalar offset so = (row - r0) * ld.  Pixels outside the image read as zero
-// (Section 3.2's convention): a lane's offset is its column, replaced by 2^31
-// where the column lies outside [0, W), and rows outside the image are read
-// through a descriptor of no bytes.  The hardware range check compares the
-// lane offset plus the scalar offset with the descriptor size: valid lanes
-// stay below it and offsets of 2^31 exceed every size used here (spans are
-// kept below 2^31 bytes).  In the aligned form (4-byte aligned rows, W a
-// multiple of 4) one dword load per lane; otherwise four byte loads.
+// Reads the four pixels of a lane (columns cb .. cb+3, cb a multiple of 4) of
+// one row through a descriptor d over whole rows from a first row r0, the row
+// chosen by the scalar offset so = (row - r0) * ld.  Pixels outside the image
+// read as zero (Section 3.2's convention): a lane's offset is its column,
+// replaced by 2^31 where no column of the lane lies inside [0, W), and rows
+// outside the image are read through a descriptor of no bytes.  The hardware
+// range check compares the lane offset plus the scalar offset with the
+// descriptor size: valid lanes stay below it and offsets of 2^31 exceed every
+// size used here (spans are kept below 2^31 bytes).
+//
+// Aligned form (4-byte aligned rows, W a multiple of 4): one dword load.
+// Otherwise the descriptor starts at the 4-byte boundary at or below the
+// first row (delta bytes earlier); a row's bytes then start at a uniform
+// misalignment mis, and a lane loads the two aligned dwords that hold its
+// four bytes and extracts them with a byte funnel shift; bytes of columns
+// at or past W are masked off.  The range check rejects a dword that does
+// not fit in the descriptor, so the descriptor ends with the aligned word
+// that holds the strip's last byte: reads past that byte stay within its
+// aligned word (never in another page) and the following dword is rejected.
 constexpr uint32_t OFF_OUT = 0x80000000u;
 
 template <bool AL>
 struct LaneRow {
-    uint32_t off[AL ? 1 : 4];
+    uint32_t off;   // lane's byte offset in a row (column cb), or 2^31
+    uint32_t keep;  // bytes of the lane's columns inside [0, W)
+    uint32_t delta; // misalignment of the descriptor base (unaligned form)
 
-    __device__ __forceinline__ LaneRow(int cb, int W)
+    __device__ __forceinline__ LaneRow(int cb, int W, uint32_t delta_)
+        : off((cb >= 0 && cb < W) ? (uint32_t)cb : OFF_OUT),
+          keep((cb + 4 <= W) ? 0xffffffffu : (cb < W ? (1u << (8 * (W - cb))) - 1u : 0u)),
+          delta(delta_)
     {
-#pragma unroll
-        for (int q = 0; q < (AL ? 1 : 4); ++q)
-            off[q] = (cb + q >= 0 && cb + q < W) ? (uint32_t)(cb + q) : OFF_OUT;
     }
 
     __device__ __forceinline__ uint32_t load(__amdgpu_buffer_rsrc_t d, uint32_t so) const
     {
-        if (AL) return __builtin_amdgcn_raw_buffer_load_b32(d, (int)off[0], (int)so, 0);
-        uint32_t v = 0u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            v |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, (int)off[AL ? 0 : q], (int)so, 0) << (8 * q);
-        return v;
+        if (AL) return __builtin_amdgcn_raw_buffer_load_b32(d, (int)off, (int)so, 0);
+        const uint32_t sb = delta + so;    // the row's first byte in d
+        const uint32_t mis = sb & 3u;
+        const uint32_t sa = sb - mis;      // its aligned word
+        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(d, (int)off, (int)sa, 0);
+        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(d, (int)(off + 4u), (int)sa, 0);
+        return __builtin_amdgcn_alignbyte(hi, lo, mis) & keep;
     }
 };
 
@@ -276,14 +288,21 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const int H = a.H, W = a.W, o = a.o, u = a.u;
     // vertical pass: lane owns the four columns cb .. cb+3
     const int cb = xh + COLS_PER_LANE * tid;
-    const LaneRow<AL> ld(cb, W);
     // The strip reads input rows rlo .. rhi only (its priming rows, then the
-    // entering, leaving and centre rows); one descriptor covers them.  The
-    // planner keeps this span, and the output spans below, under 2^31 bytes.
+    // entering, leaving and centre rows); one descriptor covers them (from
+    // the 4-byte boundary at or below the first row in the unaligned form).
+    // The planner keeps this span, and the output spans below, under 2^31
+    // bytes.
     const int rlo = max(y0 - o, 0), rhi = min(y1 - 1 + u, H - 1);
     const uint32_t ld32 = (uint32_t)a.ldI;
-    const uint8_t *rbase = a.I + (int64_t)rlo * a.ldI;
-    const uint32_t rspan = (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W;
+    const uint8_t *rrow = a.I + (int64_t)rlo * a.ldI;
+    const uint32_t delta = AL ? 0u : (uint32_t)((uintptr_t)rrow & 3u);
+    const uint8_t *rbase = rrow - delta;
+    // (unaligned form: rounded up to the end of the aligned word holding the
+    // last byte, since a dword that crosses the descriptor end reads zero)
+    const uint32_t rspan = AL ? (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W
+                              : (delta + (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W + 3u) & ~3u;
+    const LaneRow<AL> ld(cb, W, delta);
     // row `row` if rlo <= row <= rhi (in), else zeros
     auto row_load = [&](int row, bool in) -> uint32_t {
         return ld.load(rsrc(rbase, in ? rspan : 0u), in ? (uint32_t)(row - rlo) * ld32 : 0u);
@@ -363,7 +382,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         // All strips prime at once when the kernel starts, so this phase is
         // bound by the L2 bandwidth; more loads in flight per wavefront were
         // measured to be slower.
-        constexpr int PB = AL ? 32 : 8;
+        constexpr int PB = AL ? 32 : 16;
         const __amdgpu_buffer_rsrc_t rin = rsrc(rbase, rspan);
         int row = p0;  // p0 == rlo
         for (; row + PB - 1 <= p1; row += PB) {
@@ -852,14 +871,18 @@ size_t batch_workspace_bytes(int count)
 
 int batch_variant(const BoxJob *jobs, int count)
 {
+    // the unaligned row loader is correct for aligned rows as well, so a
+    // batch that mixes the two runs the unaligned variant
     int v = -2;
+    bool all_aligned = true;
     for (int i = 0; i < count; ++i) {
         const BoxJob &j = jobs[i];
-        const int vi = (j.mode == MODE_NIBLACK ? 4 : 0) + (j.aligned ? 2 : 0) + (j.mean != nullptr ? 1 : 0);
+        const int vi = (j.mode == MODE_NIBLACK ? 4 : 0) + (j.mean != nullptr ? 1 : 0);
+        all_aligned = all_aligned && j.aligned;
         if (v == -2) v = vi;
         else if (v != vi) return -1;
     }
-    return v < 0 ? -1 : v;
+    return v < 0 ? -1 : v + (all_aligned ? 2 : 0);
 }
 
 namespace {

@@ -92,6 +92,26 @@ def test_sums_unaligned_strided(bz, off, ld):
     assert np.array_equal(u32(S1), r1) and np.array_equal(u32(S2), r2)
 
 
+@pytest.mark.parametrize("off,W", [(0, 497), (1, 498), (2, 499), (3, 501), (1, 7), (2, 2)])
+def test_unaligned_width_tight_rows(bz, off, W):
+    # widths that are not multiples of 4, rows packed at a stride of W and a
+    # shifted base: every row starts at a different misalignment, the last
+    # lane of a row holds fewer than four columns, and the image ends at the
+    # end of its buffer
+    H = 150
+    buf = np.random.default_rng(W).integers(0, 256, size=(H * W + off,), dtype=np.uint8)
+    d = dev(buf)
+    view = d[off:].view(H, W)
+    host = buf[off:].reshape(H, W)
+    for h, w in ((17, 24), (1, 3), (31, 9)):
+        S1, S2 = bz.window_sums(view, h, w)
+        r1, r2 = oracle.sums_recursive(np.ascontiguousarray(host), h, w)
+        assert np.array_equal(u32(S1), r1) and np.array_equal(u32(S2), r2), (off, W, h, w)
+    mask, m, s = bz.sauvola(view, 15, 15, k=0.5, R=128.0)
+    ref = oracle.sauvola(np.ascontiguousarray(host), 15, 15, k=0.5, R=128.0)
+    assert mask_report(mask.cpu().numpy(), ref, host) == 0
+
+
 def check_moments(m, s, ref, S1, S2, n):
     m = m.cpu().numpy().astype(np.float64)
     s = s.cpu().numpy().astype(np.float64)
