@@ -74,6 +74,18 @@ def cpu_baseline(I, h, w, k, R, seconds):
     }
 
 
+def warm_gpu(step, seconds=0.3):
+    """Run steps for a fixed time so the clocks are up before timing."""
+    import torch
+    t = time.time()
+    i = 0
+    while time.time() - t < seconds:
+        for _ in range(20):
+            step(i)
+            i += 1
+        torch.cuda.synchronize()
+
+
 def _timeit(fn, n, warm=3):
     """Median per-call time in microseconds of fn(i) over n calls (HIP events
     on the current stream around each call)."""
@@ -268,6 +280,7 @@ def extras(sets, host, args):
                                             "G_updates_s": round(2.0 * win * npx / us / 1e3, 1)}
         return res
 
+    warm_gpu(lambda i: page_call("sauvola", 75, True, i))
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
     guarded("mean_std_w75", mean_std)
@@ -332,11 +345,11 @@ def main():
 
     for i in range(args.warmup):
         step(i)
-    torch.cuda.synchronize()
+    warm_gpu(step)
     stream = torch.cuda.current_stream(dev)
     # Timed region: K back-to-back steps between two events on the stream the
-    # kernel runs on.  One step is one launch, so the per-step time is the
-    # kernel's average launch duration (rocprofv3's kernel trace agrees).
+    # kernel runs on.  One step is one launch; the per-step time includes the
+    # host launch gap between consecutive kernels.
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -347,11 +360,28 @@ def main():
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
 
+    # Kernel duration for the roofline: the same launches replayed from a HIP
+    # graph (one node per buffer set), which removes most of the host launch
+    # gap between back-to-back kernels; HIP events on the capturing stream.
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(len(sets)):
+            step(i)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // len(sets))
+    t0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = t0.elapsed_time(t1) / (reps * len(sets))
+
     px = H * W
     ms_per_step = total_ms / args.steps
     value = px / (ms_per_step * 1e-3) / 1e9
     alg_bytes = 10.0 * px
-    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     traffic = read_traffic(px)
     out = {
         "metric": METRIC,
@@ -372,7 +402,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_box<MODE_SAUVOLA>",
-                     "launch_us_mean": round(ms_per_step * 1e3, 3),
+                     "launch_us_mean": round(launch_ms * 1e3, 3),
+                     "launch_us_source": "HIP events around graph replays of the step's launches",
                      "algorithmic_bytes": int(alg_bytes)},
     }
     if not args.no_cpu:
