@@ -42,8 +42,10 @@ typedef void *bz_stream; /* hipStream_t */
 typedef enum {
     BZ_OK = 0,
     BZ_ERR_INVALID = 1,   /* bad size, stride, pointer or parameter */
-    BZ_ERR_RANGE = 2,     /* h or w above 257, sizes beyond 2^31, or h rows of the
-                             image (h * ld + W bytes) spanning 2^31 bytes or more */
+    BZ_ERR_RANGE = 2,     /* h or w above 257, sizes beyond 2^31, h rows of the
+                             image (h * ld + W bytes) spanning 2^31 bytes or more,
+                             or one float32 image of the soft calls spanning
+                             ((H - 1) * ld + W) 2^29 elements or more */
     BZ_ERR_ALIAS = 3,     /* an output overlaps the input */
     BZ_ERR_WORKSPACE = 4, /* caller workspace too small */
     BZ_ERR_HIP = 5        /* the HIP runtime reported an error */

@@ -364,6 +364,8 @@ bz_status check_soft(const float *I, int B, int H, int W, ptrdiff_t ld, int h, i
     if (!isfinite(tau) || !(tau > 0.0f)) return BZ_ERR_INVALID;
     if (!aligned(I, 4)) return BZ_ERR_INVALID;
     if ((int64_t)B * H * (int64_t)ld > ((int64_t)1 << 40)) return BZ_ERR_RANGE;
+    // one image (and one dense H x W field) spans under 2^31 bytes
+    if ((int64_t)(H - 1) * ld + W >= ((int64_t)1 << 29)) return BZ_ERR_RANGE;
     return BZ_OK;
 }
 

@@ -13,15 +13,20 @@
 //           q-r .. q+l-1), so it reuses the same sliding-sum machinery with the
 //           extents swapped.
 //
-// Three kernels: k_soft<FWD> (sums -> y), k_soft<BWD1> (sums -> G1, G2,
-// delta/tau and per-workgroup partials of dL/dk, dL/dR), k_soft<ADJ> (adjoint
-// sums of G1, G2 -> dL/dI), and k_soft_reduce (fixed-order reduction of the
-// partials, so the k and R gradients are deterministic).  Nothing is saved by
-// the forward: the backward recomputes m and s from I.
+// Three phases of one tile kernel: FWD (sums -> y), BWD1 (sums -> G1, G2,
+// delta/tau and per-workgroup partials of dL/dk, dL/dR) and ADJ (adjoint
+// sums of G1, G2 -> dL/dI), then k_soft_reduce (fixed-order reduction of
+// the partials, so the k and R gradients are deterministic).  Nothing is
+// saved by the forward: the backward recomputes m and s from I.
 //
-// Sums are binary64: vertical running sums per lane column (add the entering
-// row, subtract the leaving row) and a row prefix per tile (DPP wave scan plus
-// an LDS cross-wave combine), differenced at the window ends.
+// Layout of a tile (as in the box kernels): lane t owns four adjacent columns
+// for the vertical running sums, loaded as one 16-byte vector per row when
+// rows allow it; the running sums and the row prefixes are binary64 (the
+// inputs are real-valued, so float32 running sums would drift); the epilogue
+// lane takes columns t, t+64, t+128, t+192 of its wave's 256, so prefix
+// reads are conflict-free and each load or store instruction covers 64
+// consecutive elements.  Per-pixel arithmetic after the sums is float32,
+// except n S2 - S1^2, which is formed in binary64 to avoid cancellation.
 #include "../../include/binarize.h"
 #include "internal.hpp"
 
@@ -35,7 +40,14 @@ enum Phase { FWD = 0, BWD1 = 1, ADJ = 2 };
 
 constexpr int SOFT_THREADS = 256;
 constexpr int SOFT_WAVES = SOFT_THREADS / 64;
-constexpr int SR = 2;  // rows per barrier pair
+constexpr int SNH = 4 * SOFT_THREADS;  // halo'd columns of a tile
+// Prefix row (binary64) of a tile: index i (0 = empty prefix) at SLPAD + i;
+// the SLPAD entries below hold zeros and the SRPAD entries above repeat the
+// tile total, so windows reaching past either end need no clamp.
+constexpr int SLPAD = 131;
+constexpr int SRPAD = 256;
+constexpr int SPS = SLPAD + 1 + SNH + SRPAD;
+constexpr uint32_t SOFF_OUT = 0x80000000u;
 
 struct SoftArgs {
     const float *I;     // B images, image b at I + b*H*ld
@@ -53,6 +65,7 @@ struct SoftArgs {
     int eo, eu, el, er; // extents summed by this phase
     float tau;
     int tile_w, ntx, halo_l, strip, nsy;
+    int vec;            // rows allow 16-byte loads (ld and W multiples of 4)
 };
 
 __device__ __forceinline__ int xcd_remap_s(int b, int n)
@@ -60,6 +73,11 @@ __device__ __forceinline__ int xcd_remap_s(int b, int n)
     const int q = n >> 3, rem = n & 7;
     const int x = b & 7, i = b >> 3;
     return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t srsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
 template <int CTRL, int ROW_MASK>
@@ -70,6 +88,7 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
+// inclusive prefix over the 64 lanes, in a fixed order
 __device__ __forceinline__ double wave_scan_f64(double v)
 {
     v += dpp_f64<0x111, 0xf>(v);
@@ -81,46 +100,59 @@ __device__ __forceinline__ double wave_scan_f64(double v)
     return v;
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v)
+// inclusive prefix over the first 16 lanes
+__device__ __forceinline__ double row_scan16_f64(double v)
 {
-    // fixed-order reduction: the inclusive scan's last lane holds the total
-    v = wave_scan_f64(v);
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
-                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+    v += dpp_f64<0x111, 0xf>(v);
+    v += dpp_f64<0x112, 0xf>(v);
+    v += dpp_f64<0x114, 0xf>(v);
+    v += dpp_f64<0x118, 0xf>(v);
+    return v;
 }
 
-// The four values X1 (and X2) of a lane's columns in one row.  FWD/BWD1 sum
-// I and I^2; ADJ sums G1 and G2.  Out-of-image columns and rows are zero.
-template <int PH>
-__device__ __forceinline__ void row_vals(const SoftArgs &a, int b, int row, int cb, double x1[4],
-                                         double x2[4])
+__device__ __forceinline__ double lane_f64(double v, int l)
 {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Four adjacent floats of one row (columns cb .. cb+3) through a descriptor
+// over whole rows, the row chosen by the scalar byte offset so.  VEC: one
+// 16-byte load (all four columns inside or outside the image together);
+// otherwise four dword loads with per-column offsets.  Offsets of 2^31 (and
+// descriptors of no bytes, for rows outside the image) read zero.
+template <bool VEC>
+struct QuadLoader {
+    uint32_t off[4];
+    __device__ __forceinline__ QuadLoader(int cb, int W)
+    {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = cb + k;
-        float v1 = 0.0f, v2 = 0.0f;
-        if (c >= 0 && c < a.W) {
-            if (PH == ADJ) {
-                const int64_t off = ((int64_t)b * a.H + row) * a.W + c;
-                v1 = a.G1[off];
-                v2 = a.G2[off];
-            } else {
-                v1 = a.I[((int64_t)b * a.H + row) * a.ld + c];
-            }
-        }
-        x1[k] = (double)v1;
-        x2[k] = (PH == ADJ) ? (double)v2 : (double)v1 * (double)v1;  // exact square
+        for (int q = 0; q < 4; ++q)
+            off[q] = (cb + q >= 0 && cb + q < W) ? 4u * (uint32_t)(cb + q) : SOFF_OUT;
     }
-}
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t d, uint32_t so, float v[4]) const
+    {
+        if (VEC) {
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i x = __builtin_amdgcn_raw_buffer_load_b128(d, (int)off[0], (int)so, 0);
+            v[0] = __int_as_float(x[0]);
+            v[1] = __int_as_float(x[1]);
+            v[2] = __int_as_float(x[2]);
+            v[3] = __int_as_float(x[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(d, (int)off[q], (int)so, 0));
+        }
+    }
+};
 
-template <int PH>
+template <int PH, bool VEC>
 __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
 {
     constexpr int NT = SOFT_THREADS;
-    constexpr int NH = 4 * NT;
-    constexpr int PS = NH + 4;
-    __shared__ double P[SR][2][PS];
-    __shared__ double Tot[SR][2][SOFT_WAVES];
+    __shared__ double P[2][SPS];             // prefix rows of S1 and S2
+    __shared__ double Tot[2][SOFT_WAVES];    // wave totals
     __shared__ double Red[2][SOFT_WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -135,142 +167,189 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
     const int xh = (tx == 0) ? 0 : x0 - a.halo_l;
     const int cb = xh + 4 * tid;
     const int H = a.H, W = a.W;
+    const int64_t ld = a.ld;
 
-    if (tid < SR) {
-        P[tid][0][0] = 0.0;
-        P[tid][1][0] = 0.0;
-    }
-    int ai[4], bi[4];
-    double ncd[4];
-    bool valid[4];
+    for (int i = tid; i < 2 * (SLPAD + 1); i += NT) P[i / (SLPAD + 1)][i % (SLPAD + 1)] = 0.0;
+
+    // rows read by the vertical pass: rlo .. rhi of image b
+    const int rlo = max(y0 - a.eo, 0), rhi = min(y1 - 1 + a.eu, H - 1);
+    const QuadLoader<VEC> ql(cb, W);
+    const int64_t pitch = (PH == ADJ) ? (int64_t)W : ld;  // rows of the summed fields
+    const uint32_t span = (uint32_t)(4 * ((int64_t)(rhi - rlo) * pitch + W));
+    const float *src1 = (PH == ADJ) ? a.G1 : a.I;
+    // X1, X2 of a row: (I, I^2) or (G1, G2); rows outside [rlo, rhi] are zero
+    auto row_vals = [&](int row, double x1[4], double x2[4]) {
+        const bool in = row >= rlo && row <= rhi;
+        const uint32_t so = in ? (uint32_t)(4 * (int64_t)(row - rlo) * pitch) : 0u;
+        float v1[4], v2[4];
+        ql.load(srsrc(src1 + ((int64_t)b * H + rlo) * pitch, in ? span : 0u), so, v1);
+        if (PH == ADJ)
+            ql.load(srsrc(a.G2 + ((int64_t)b * H + rlo) * pitch, in ? span : 0u), so, v2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int j = cb + k;
-        valid[k] = (j >= x0) && (j < x1);
-        const int ar = min(j + a.er, W - 1), bl = max(j - a.el, -1);
-        ai[k] = valid[k] ? ar - xh + 1 : 0;
-        bi[k] = valid[k] ? bl - xh + 1 : 0;
-        // the forward count (the adjoint sums need none)
-        ncd[k] = (double)(min(j + a.r, W - 1) - max(j - a.l, -1));
-    }
+        for (int q = 0; q < 4; ++q) {
+            x1[q] = (double)v1[q];
+            x2[q] = (PH == ADJ) ? (double)v2[q] : (double)v1[q] * (double)v1[q];  // exact square
+        }
+    };
 
-    double kb = 0.0, R64 = 0.0;
-    if (PH != ADJ) {
-        kb = (double)a.k[b];
-        R64 = (double)a.R[0];
+    // epilogue columns x0 + eo + 64 j (j = 0..3) and their element offsets
+    const int eo = 256 * wave + lane;
+    const int ec0 = x0 + eo;
+    const int ai0 = SLPAD + ec0 + a.er - xh + 1;  // prefix index of j + er
+    const int bi0 = SLPAD + ec0 - a.el - xh + 1;  // prefix index of j - el
+    uint32_t oe[4];  // byte offset of the column in a row, 2^31 outside the tile
+    double ncd[4], rnc[4];  // forward column counts and their reciprocals
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = ec0 + 64 * j;
+        oe[j] = (c < x1) ? 4u * (uint32_t)c : SOFF_OUT;
+        ncd[j] = (double)max(min(c + a.r, W - 1) - max(c - a.l, -1), 1);
+        rnc[j] = 1.0 / ncd[j];
     }
-    const double tau = (double)a.tau;
+    // descriptors of the epilogue's per-pixel rows of image b (byte offset of
+    // row y: 4 y pitch); the planner keeps image spans under 2^31 bytes
+    const uint32_t img_bytes = (uint32_t)(4 * ((int64_t)(H - 1) * ld + W));
+    const uint32_t fld_bytes = (uint32_t)(4 * (int64_t)H * W);
+    const __amdgpu_buffer_rsrc_t dI = srsrc(a.I + (int64_t)b * H * ld, img_bytes);
+
+    float kb = 0.0f, kR = 0.0f;
+    double kb64 = 0.0, rR64 = 1.0, cR64 = 0.0;
+    if (PH != ADJ) {
+        kb = a.k[b];
+        kb64 = (double)kb;
+        rR64 = 1.0 / (double)a.R[0];
+        kR = (float)(kb64 * rR64);
+        cR64 = -kb64 * rR64 * rR64;  // dt/dR = -k m s / R^2
+    }
+    const float rtau = 1.0f / a.tau;
+    const double rtau64 = 1.0 / (double)a.tau;
 
     // priming: rows y0-eo .. y0+eu-1
     double C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
     for (int row = max(y0 - a.eo, 0); row <= min(y0 + a.eu - 1, H - 1); ++row) {
         double x1v[4], x2v[4];
-        row_vals<PH>(a, b, row, cb, x1v, x2v);
+        row_vals(row, x1v, x2v);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            C[k] += x1v[k];
-            D[k] += x2v[k];
+        for (int q = 0; q < 4; ++q) {
+            C[q] += x1v[q];
+            D[q] += x2v[q];
         }
     }
 
     double dk_acc = 0.0, dR_acc = 0.0;
-    for (int yg = y0; yg < y1; yg += SR) {
-        double pc[SR][4], pd[SR][4], sc[SR], sd[SR];
+    for (int y = y0; y < y1; ++y) {
+        {
+            double e1[4], e2[4], l1[4], l2[4];
+            row_vals(y + a.eu, e1, e2);
+            row_vals(y - a.eo, l1, l2);
 #pragma unroll
-        for (int r = 0; r < SR; ++r) {
-            const int y = yg + r;
-            if (y < y1) {
-                double e1[4], e2[4], l1[4], l2[4];
-                const int ra = y + a.eu, rb = y - a.eo;
-                if (ra < H) row_vals<PH>(a, b, ra, cb, e1, e2);
-                else { for (int k = 0; k < 4; ++k) { e1[k] = 0.0; e2[k] = 0.0; } }
-                if (rb >= 0) row_vals<PH>(a, b, rb, cb, l1, l2);
-                else { for (int k = 0; k < 4; ++k) { l1[k] = 0.0; l2[k] = 0.0; } }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    C[k] = (C[k] + e1[k]) - l1[k];
-                    D[k] = (D[k] + e2[k]) - l2[k];
-                }
+            for (int q = 0; q < 4; ++q) {
+                C[q] = (C[q] + e1[q]) - l1[q];
+                D[q] = (D[q] + e2[q]) - l2[q];
             }
-            pc[r][0] = C[0]; pc[r][1] = pc[r][0] + C[1]; pc[r][2] = pc[r][1] + C[2]; pc[r][3] = pc[r][2] + C[3];
-            pd[r][0] = D[0]; pd[r][1] = pd[r][0] + D[1]; pd[r][2] = pd[r][1] + D[2]; pd[r][3] = pd[r][2] + D[3];
-            sc[r] = wave_scan_f64(pc[r][3]);
-            sd[r] = wave_scan_f64(pd[r][3]);
-            if (lane == 63) {
-                Tot[r][0][wave] = sc[r];
-                Tot[r][1][wave] = sd[r];
+        }
+        double pc[4], pd[4];
+        pc[0] = C[0]; pc[1] = pc[0] + C[1]; pc[2] = pc[1] + C[2]; pc[3] = pc[2] + C[3];
+        pd[0] = D[0]; pd[1] = pd[0] + D[1]; pd[2] = pd[1] + D[2]; pd[3] = pd[2] + D[3];
+        const double sc = wave_scan_f64(pc[3]);
+        const double sd = wave_scan_f64(pd[3]);
+        if (lane == 63) {
+            Tot[0][wave] = sc;
+            Tot[1][wave] = sd;
+        }
+        __syncthreads();
+        {
+            // offsets of the wave totals (fixed order); lanes past the waves
+            // never feed lanes below them
+            const double wc = row_scan16_f64(lane < SOFT_WAVES ? Tot[0][lane & (SOFT_WAVES - 1)] : 0.0);
+            const double wd = row_scan16_f64(lane < SOFT_WAVES ? Tot[1][lane & (SOFT_WAVES - 1)] : 0.0);
+            const double oc = (wave > 0) ? lane_f64(wc, max(wave - 1, 0)) : 0.0;
+            const double od = (wave > 0) ? lane_f64(wd, max(wave - 1, 0)) : 0.0;
+            const double ec = (sc - pc[3]) + oc, ed = (sd - pd[3]) + od;
+            double *p1 = &P[0][SLPAD + 1 + 4 * tid];
+            double *p2 = &P[1][SLPAD + 1 + 4 * tid];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                p1[q] = pc[q] + ec;
+                p2[q] = pd[q] + ed;
+            }
+            if (wave == SOFT_WAVES - 1) {  // right pad: the tile totals
+                const double tc = lane_f64(wc, SOFT_WAVES - 1), td = lane_f64(wd, SOFT_WAVES - 1);
+#pragma unroll
+                for (int q = 0; q < SRPAD / 64; ++q) {
+                    P[0][SLPAD + 1 + SNH + 64 * q + lane] = tc;
+                    P[1][SLPAD + 1 + SNH + 64 * q + lane] = td;
+                }
             }
         }
         __syncthreads();
+
+        const uint32_t soI = (uint32_t)(4 * (int64_t)y * ld);
+        const uint32_t soF = (uint32_t)(4 * (int64_t)y * W);
+        const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
+        const double rnr = 1.0 / (double)nr;
 #pragma unroll
-        for (int r = 0; r < SR; ++r) {
-            double oc = 0.0, od = 0.0;
-            for (int w2 = 0; w2 < wave; ++w2) {  // fixed order
-                oc += Tot[r][0][w2];
-                od += Tot[r][1][w2];
+        for (int j = 0; j < 4; ++j) {
+            const double S1 = P[0][ai0 + 64 * j] - P[0][bi0 + 64 * j];
+            const double S2 = P[1][ai0 + 64 * j] - P[1][bi0 + 64 * j];
+            const float Iv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dI, (int)oe[j], (int)soI, 0));
+            if (PH == ADJ) {
+                const __amdgpu_buffer_rsrc_t ddd = srsrc(a.dd + (int64_t)b * H * W, fld_bytes);
+                const float dv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(ddd, (int)oe[j], (int)soF, 0));
+                const float g = dv + (float)S1 + 2.0f * Iv * (float)S2;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g), srsrc(a.gI + (int64_t)b * H * ld, img_bytes),
+                                                      (int)oe[j], (int)soI, 2);
+                continue;
             }
-            const double ec = (sc[r] - pc[r][3]) + oc, ed = (sd[r] - pd[r][3]) + od;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                P[r][0][1 + 4 * tid + k] = pc[r][k] + ec;
-                P[r][1][1 + 4 * tid + k] = pd[r][k] + ed;
+            // the threshold and z in binary64 (z decides delta, which every
+            // gradient scales), the sigmoid and what follows in float32
+            const double rn64 = rnr * rnc[j];
+            const double n = (double)nr * ncd[j];
+            const double m64 = S1 * rn64;
+            const double vn = __builtin_fma(n, S2, -(S1 * S1));
+            const double s64 = vn > 0.0 ? __builtin_sqrt(vn) * rn64 : 0.0;
+            const double q64 = __builtin_fma(s64, rR64, -1.0);     // s/R - 1
+            const double t64 = m64 * __builtin_fma(kb64, q64, 1.0);
+            const float z = (float)(((double)Iv - t64) * rtau64);
+            // sigmoid through e^-|z| <= 1: y and y (1 - y) = e / (1 + e)^2
+            // keep their relative accuracy at both tails
+            const float ea = __expf(-fabsf(z));
+            const float rr = 1.0f / (1.0f + ea);
+            const float yv = (z >= 0.0f ? 1.0f : ea) * rr;
+            if (PH == FWD) {
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(yv), srsrc(a.y + (int64_t)b * H * ld, img_bytes),
+                                                      (int)oe[j], (int)soI, 2);
+                continue;
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < SR; ++r) {
-            const int y = yg + r;
-            if (y >= y1) continue;
-            const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!valid[k]) continue;
-                const int j = cb + k;
-                const double S1 = P[r][0][ai[k]] - P[r][0][bi[k]];
-                const double S2 = P[r][1][ai[k]] - P[r][1][bi[k]];
-                const int64_t pix = ((int64_t)b * H + y) * a.ld + j;
-                if (PH == ADJ) {
-                    const int64_t g = ((int64_t)b * H + y) * W + j;
-                    a.gI[pix] = (float)((double)a.dd[g] + S1 + 2.0 * (double)a.I[pix] * S2);
-                    continue;
-                }
-                const double n = (double)nr * ncd[k];
-                const double m = S1 / n;
-                double v = (n * S2 - S1 * S1) / (n * n);
-                if (v < 0.0) v = 0.0;
-                const double s = sqrt(v);
-                const double q = s / R64 - 1.0;
-                const double t = m * (1.0 + kb * q);
-                const double Iv = (double)a.I[pix];
-                const double z = (Iv - t) / tau;
-                const double yv = 1.0 / (1.0 + exp(-z));
-                if (PH == FWD) {
-                    a.y[pix] = (float)yv;
-                    continue;
-                }
-                const double delta = (double)a.gy[pix] * yv * (1.0 - yv);
-                const double e = -delta / tau;
-                dk_acc += e * m * q;
-                dR_acc += e * (-kb * m * s / (R64 * R64));
-                const double aa = e * (1.0 + kb * q);
-                const double beta = e * kb * m / R64;
-                double g1, g2;
-                if (s > 0.0) {
-                    g1 = aa / n - beta * m / (n * s);
-                    g2 = beta / (2.0 * n * s);
-                } else {
-                    g1 = aa / n;
-                    g2 = 0.0;
-                }
-                const int64_t g = ((int64_t)b * H + y) * W + j;
-                a.G1[g] = (float)g1;
-                a.G2[g] = (float)g2;
-                a.dd[g] = (float)(delta / tau);
+            const float gv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                srsrc(a.gy + (int64_t)b * H * ld, img_bytes), (int)oe[j], (int)soI, 0));
+            const float delta = gv * (ea * rr * rr);
+            const float e = -delta * rtau;
+            const bool in = oe[j] != SOFF_OUT;
+            dk_acc += in ? (double)e * (m64 * q64) : 0.0;
+            dR_acc += in ? (double)e * (m64 * s64 * cR64) : 0.0;
+            const float m = (float)m64, s = (float)s64, q = (float)q64, rn = (float)rn64;
+            const float aa = e * __builtin_fmaf(kb, q, 1.0f);
+            const float beta = e * kR * m;
+            float g1, g2;
+            if (s > 0.0f) {
+                const float rns = rn / s;
+                g1 = aa * rn - beta * m * rns;
+                g2 = 0.5f * beta * rns;
+            } else {
+                g1 = aa * rn;
+                g2 = 0.0f;
             }
+            const __amdgpu_buffer_rsrc_t f1 = srsrc(a.G1 + (int64_t)b * H * W, fld_bytes);
+            const __amdgpu_buffer_rsrc_t f2 = srsrc(a.G2 + (int64_t)b * H * W, fld_bytes);
+            const __amdgpu_buffer_rsrc_t f3 = srsrc(a.dd + (int64_t)b * H * W, fld_bytes);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g1), f1, (int)oe[j], (int)soF, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g2), f2, (int)oe[j], (int)soF, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(delta * rtau), f3, (int)oe[j], (int)soF, 0);
         }
     }
     if (PH == BWD1) {
-        const double wk = wave_sum_f64(dk_acc), wr = wave_sum_f64(dR_acc);
+        const double wk = lane_f64(wave_scan_f64(dk_acc), 63), wr = lane_f64(wave_scan_f64(dR_acc), 63);
         if (lane == 0) {
             Red[0][wave] = wk;
             Red[1][wave] = wr;
@@ -313,8 +392,7 @@ void plan_soft(SoftArgs &a)
     a.u = a.h / 2;
     a.l = (a.w + 1) / 2;
     a.r = a.w / 2;
-    constexpr int NH = 4 * SOFT_THREADS;
-    if (a.W <= NH) {
+    if (a.W <= SNH) {
         a.tile_w = a.W;
         a.ntx = 1;
         a.halo_l = 0;
@@ -322,27 +400,36 @@ void plan_soft(SoftArgs &a)
         const int lmax = (a.l > a.r + 1) ? a.l : a.r + 1;   // forward l or adjoint r+1
         const int rmax = (a.r > a.l - 1) ? a.r : a.l - 1;   // forward r or adjoint l-1
         a.halo_l = ((lmax - 1) + 3) & ~3;
-        a.tile_w = (NH - a.halo_l - rmax) & ~3;
+        a.tile_w = (SNH - a.halo_l - rmax) & ~3;
         a.ntx = (a.W + a.tile_w - 1) / a.tile_w;
     }
-    // about 4 workgroups per CU over the whole batch
-    const long target = 1024;
-    int strip = (int)(((long)a.B * a.H * a.ntx + target - 1) / target);
-    if (strip < 2 * a.h) strip = 2 * a.h;
+    // strips depend on the image geometry only, so an image gives the same
+    // bits in any batch; the priming of a strip reads h rows beyond it
+    int strip = a.h < 32 ? a.h : 32;
+    if (strip < 8) strip = 8;
     if (strip > a.H) strip = a.H;
     a.strip = strip;
     a.nsy = (a.H + strip - 1) / strip;
+    a.vec = (a.ld % 4 == 0) && (a.W % 4 == 0);
 }
 
 size_t soft_fields_bytes(int B, int H, int W) { return (size_t)B * H * W * sizeof(float); }
+
+template <int PH>
+void launch_phase(const SoftArgs &a, int blocks, hipStream_t st)
+{
+    if (a.vec) hipLaunchKernelGGL((k_soft<PH, true>), dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+    else hipLaunchKernelGGL((k_soft<PH, false>), dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+}
 
 }  // namespace
 
 size_t soft_workspace_bytes(int B, int H, int W)
 {
-    // partial slots for any window: a column tile is at least 4*256 - 2*132
-    // columns wide and a strip at least 2 rows tall
-    const size_t tiles = (size_t)B * ((W + 759) / 760) * ((H + 1) / 2);
+    // one partial pair per workgroup: column tiles are at least
+    // 1024 - 2 * 128 columns wide (windows up to 257) and strips at least 8
+    // rows tall (or the whole image)
+    const size_t tiles = (size_t)B * ((W + 767) / 768) * (size_t)((H + 7) / 8);
     const size_t parts = tiles * 2 * sizeof(double);
     return 3 * ((soft_fields_bytes(B, H, W) + 255) & ~(size_t)255) + ((parts + 255) & ~(size_t)255);
 }
@@ -368,8 +455,7 @@ hipError_t launch_soft_fwd(const float *I, int B, int H, int W, int64_t ld, int 
     a.eu = a.u;
     a.el = a.l;
     a.er = a.r;
-    const int blocks = B * a.ntx * a.nsy;
-    hipLaunchKernelGGL(k_soft<FWD>, dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+    launch_phase<FWD>(a, B * a.ntx * a.nsy, st);
     return hipGetLastError();
 }
 
@@ -404,7 +490,7 @@ hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W,
     a.eu = a.u;
     a.el = a.l;
     a.er = a.r;
-    hipLaunchKernelGGL(k_soft<BWD1>, dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+    launch_phase<BWD1>(a, blocks, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the reflected window: rows q-u .. q+o-1, columns q-r .. q+l-1
@@ -412,7 +498,9 @@ hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W,
     a.eu = a.o - 1;
     a.el = a.r + 1;
     a.er = a.l - 1;
-    hipLaunchKernelGGL(k_soft<ADJ>, dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+    // the dense fields have row stride W: 16-byte loads need W % 4 == 0
+    a.vec = (W % 4 == 0);
+    launch_phase<ADJ>(a, blocks, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(64), 0, st, (const double *)a.part, B, per_img,
