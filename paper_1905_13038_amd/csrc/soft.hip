@@ -38,15 +38,27 @@ namespace {
 
 enum Phase { FWD = 0, BWD1 = 1, ADJ = 2 };
 
-constexpr int SOFT_THREADS = 256;
-constexpr int SOFT_WAVES = SOFT_THREADS / 64;
-constexpr int SNH = 4 * SOFT_THREADS;  // halo'd columns of a tile
-// Prefix row (binary64) of a tile: index i (0 = empty prefix) at SLPAD + i;
-// the SLPAD entries below hold zeros and the SRPAD entries above repeat the
-// tile total, so windows reaching past either end need no clamp.
-constexpr int SLPAD = 131;
-constexpr int SRPAD = 256;
-constexpr int SPS = SLPAD + 1 + SNH + SRPAD;
+// Two tile shapes: a workgroup of 4 waves over 1024 halo'd columns (any
+// window up to 257), and a single wave for rows of at most 256 columns (no
+// workgroup barriers: the wave owns its prefix rows).  Single-wave tiles
+// over wider rows would repeat their halo columns in every tile; measured
+// on 1024-column rows at h = w = 32 that costs more than the barriers of
+// the four-wave tile save.
+template <int NT>
+struct SoftTile {
+    static constexpr int WAVES = NT / 64;
+    static constexpr int SNH = 4 * NT;  // halo'd columns of a tile
+    // Prefix row (binary64) of a tile: index i (0 = empty prefix) at LPAD + i;
+    // the LPAD entries below hold zeros and the RPAD entries above repeat the
+    // tile total, so windows reaching past either end need no clamp.  The
+    // single-wave tile takes windows with max(l, r + 1) <= 65 and
+    // max(r, l - 1) <= 64.
+    static constexpr int LPAD = NT == 64 ? 67 : 131;
+    static constexpr int RPAD = NT == 64 ? 64 : 256;
+    static constexpr int PS = LPAD + 1 + SNH + RPAD;
+};
+constexpr int WIDE_THREADS = 256;
+constexpr int WAVE_THREADS = 64;
 constexpr uint32_t SOFF_OUT = 0x80000000u;
 
 struct SoftArgs {
@@ -65,6 +77,7 @@ struct SoftArgs {
     int eo, eu, el, er; // extents summed by this phase
     float tau;
     int tile_w, ntx, halo_l, strip, nsy;
+    int nt;             // tile shape: 64 (one wave) or 256 threads
     int vec;            // rows allow 16-byte loads (ld and W multiples of 4)
 };
 
@@ -100,20 +113,35 @@ __device__ __forceinline__ double wave_scan_f64(double v)
     return v;
 }
 
-// inclusive prefix over the first 16 lanes
-__device__ __forceinline__ double row_scan16_f64(double v)
-{
-    v += dpp_f64<0x111, 0xf>(v);
-    v += dpp_f64<0x112, 0xf>(v);
-    v += dpp_f64<0x114, 0xf>(v);
-    v += dpp_f64<0x118, 0xf>(v);
-    return v;
-}
-
 __device__ __forceinline__ double lane_f64(double v, int l)
 {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                             __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// 1/n for a count n >= 1: a float32 estimate refined by two binary64
+// Newton steps (relative error below 2^-52).
+__device__ __forceinline__ double recip64(int n)
+{
+    const double d = (double)n;
+    double r = (double)__builtin_amdgcn_rcpf((float)n);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// sqrt(v) for v > 0 (0 for v <= 0): a float32 square root refined by one
+// binary64 Newton step, relative error about 2^-46 (both float32 estimates
+// carry about 2^-23).  Values below the float32 normal range take the
+// binary64 square root.
+__device__ __forceinline__ double sqrt_pos(double v)
+{
+    const float vf = (float)v;
+    if (!(vf >= 0x1p-100f)) return v > 0.0 ? __builtin_sqrt(v) : 0.0;
+    const float sf = __builtin_amdgcn_sqrtf(vf);
+    const double x = (double)sf;
+    const double h = 0.5 * (double)__builtin_amdgcn_rcpf(sf);
+    return __builtin_fma(__builtin_fma(-x, x, v), h, x);
 }
 
 // Four adjacent floats of one row (columns cb .. cb+3) through a descriptor
@@ -147,12 +175,15 @@ struct QuadLoader {
     }
 };
 
-template <int PH, bool VEC>
-__global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
+template <int PH, bool VEC, int NT>
+__global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
 {
-    constexpr int NT = SOFT_THREADS;
-    __shared__ double P[2][SPS];             // prefix rows of S1 and S2
-    __shared__ double Tot[2][SOFT_WAVES];    // wave totals
+    using T = SoftTile<NT>;
+    constexpr int SLPAD = T::LPAD, SRPAD = T::RPAD, SNH = T::SNH, SOFT_WAVES = T::WAVES;
+    static_assert(NT == 64 || NT == 256, "tile shapes: one wave, or four");
+    __shared__ double P[2][T::PS];               // prefix rows of S1 and S2
+    __shared__ double Tl[2][NT == 64 ? 1 : NT];  // lane totals (4 columns each)
+    __shared__ double El[2][NT + 4];             // exclusive lane offsets, then the row total
     __shared__ double Red[2][SOFT_WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -177,18 +208,27 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
     const int64_t pitch = (PH == ADJ) ? (int64_t)W : ld;  // rows of the summed fields
     const uint32_t span = (uint32_t)(4 * ((int64_t)(rhi - rlo) * pitch + W));
     const float *src1 = (PH == ADJ) ? a.G1 : a.I;
-    // X1, X2 of a row: (I, I^2) or (G1, G2); rows outside [rlo, rhi] are zero
-    auto row_vals = [&](int row, double x1[4], double x2[4]) {
+    // raw values of a row: I, or (G1, G2); rows outside [rlo, rhi] read zero
+    const float *base1 = src1 + ((int64_t)b * H + rlo) * pitch;
+    const float *base2 = (PH == ADJ) ? a.G2 + ((int64_t)b * H + rlo) * pitch : nullptr;
+    auto load_row = [&](int row, float v1[4], float v2[4]) {
         const bool in = row >= rlo && row <= rhi;
         const uint32_t so = in ? (uint32_t)(4 * (int64_t)(row - rlo) * pitch) : 0u;
-        float v1[4], v2[4];
-        ql.load(srsrc(src1 + ((int64_t)b * H + rlo) * pitch, in ? span : 0u), so, v1);
-        if (PH == ADJ)
-            ql.load(srsrc(a.G2 + ((int64_t)b * H + rlo) * pitch, in ? span : 0u), so, v2);
+        ql.load(srsrc(base1, in ? span : 0u), so, v1);
+        if (PH == ADJ) ql.load(srsrc(base2, in ? span : 0u), so, v2);
+    };
+    // X1 += sign v1 and X2 += sign (v1^2 or v2), binary64 (squares exact)
+    auto accumulate = [&](double X1[4], double X2[4], const float v1[4], const float v2[4], bool add) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            x1[q] = (double)v1[q];
-            x2[q] = (PH == ADJ) ? (double)v2[q] : (double)v1[q] * (double)v1[q];  // exact square
+            const double d1 = (double)v1[q];
+            if (add) {
+                X1[q] += d1;
+                X2[q] = (PH == ADJ) ? X2[q] + (double)v2[q] : __builtin_fma(d1, d1, X2[q]);
+            } else {
+                X1[q] -= d1;
+                X2[q] = (PH == ADJ) ? X2[q] - (double)v2[q] : __builtin_fma(-d1, d1, X2[q]);
+            }
         }
     };
 
@@ -212,60 +252,115 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
     const uint32_t fld_bytes = (uint32_t)(4 * (int64_t)H * W);
     const __amdgpu_buffer_rsrc_t dI = srsrc(a.I + (int64_t)b * H * ld, img_bytes);
 
-    float kb = 0.0f, kR = 0.0f;
+    float kb = 0.0f, kR = 0.0f, rRf = 0.0f;
     double kb64 = 0.0, rR64 = 1.0, cR64 = 0.0;
     if (PH != ADJ) {
         kb = a.k[b];
         kb64 = (double)kb;
         rR64 = 1.0 / (double)a.R[0];
         kR = (float)(kb64 * rR64);
+        rRf = (float)rR64;
         cR64 = -kb64 * rR64 * rR64;  // dt/dR = -k m s / R^2
     }
     const float rtau = 1.0f / a.tau;
-    const double rtau64 = 1.0 / (double)a.tau;
 
-    // priming: rows y0-eo .. y0+eu-1
+    // priming: rows y0-eo .. y0+eu-1, loaded PRIME rows at a time
+    constexpr int PRIME = 8;
     double C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
-    for (int row = max(y0 - a.eo, 0); row <= min(y0 + a.eu - 1, H - 1); ++row) {
-        double x1v[4], x2v[4];
-        row_vals(row, x1v, x2v);
+    for (int r0 = y0 - a.eo; r0 < y0 + a.eu; r0 += PRIME) {
+        float v1[PRIME][4], v2[PRIME][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            C[q] += x1v[q];
-            D[q] += x2v[q];
-        }
+        for (int i = 0; i < PRIME; ++i) load_row(r0 + i < y0 + a.eu ? r0 + i : -1, v1[i], v2[i]);
+#pragma unroll
+        for (int i = 0; i < PRIME; ++i) accumulate(C, D, v1[i], v2[i], true);
     }
 
+    // the vertical pass of row y reads rows y + eu (entering) and y - eo
+    // (leaving); each row's are loaded one row ahead
+    float ne1[4], ne2[4], nl1[4], nl2[4];
+    load_row(y0 + a.eu, ne1, ne2);
+    load_row(y0 - a.eo, nl1, nl2);
     double dk_acc = 0.0, dR_acc = 0.0;
+    const __amdgpu_buffer_rsrc_t dX =  // second per-pixel input of the epilogue
+        (PH == BWD1) ? srsrc(a.gy + (int64_t)b * H * ld, img_bytes)
+                     : srsrc((PH == ADJ) ? a.dd + (int64_t)b * H * W : a.I, (PH == ADJ) ? fld_bytes : 0u);
+    // the epilogue's per-pixel inputs of a row (I, and gy or dd), loaded one
+    // row ahead; row H lies past the descriptors and reads zero
+    auto load_epi = [&](int y, float Iv[4], float Xv[4]) {
+        const uint32_t soI = (uint32_t)(4 * (int64_t)y * ld);
+        const uint32_t soF = (uint32_t)(4 * (int64_t)y * W);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Iv[j] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dI, (int)oe[j], (int)soI, 0));
+            if (PH != FWD)
+                Xv[j] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dX, (int)oe[j],
+                                                                            (int)(PH == ADJ ? soF : soI), 0));
+        }
+    };
+    float nIv[4], nXv[4];
+    load_epi(y0, nIv, nXv);
     for (int y = y0; y < y1; ++y) {
+        const uint32_t soI = (uint32_t)(4 * (int64_t)y * ld);
+        const uint32_t soF = (uint32_t)(4 * (int64_t)y * W);
+        float Ivs[4], Xvs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Ivs[j] = nIv[j];
+            Xvs[j] = (PH != FWD) ? nXv[j] : 0.0f;
+        }
+        load_epi(y + 1, nIv, nXv);
         {
-            double e1[4], e2[4], l1[4], l2[4];
-            row_vals(y + a.eu, e1, e2);
-            row_vals(y - a.eo, l1, l2);
+            float e1[4], e2[4], l1[4], l2[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                C[q] = (C[q] + e1[q]) - l1[q];
-                D[q] = (D[q] + e2[q]) - l2[q];
+                e1[q] = ne1[q];
+                e2[q] = ne2[q];
+                l1[q] = nl1[q];
+                l2[q] = nl2[q];
             }
+            load_row(y + 1 < y1 ? y + 1 + a.eu : -1, ne1, ne2);
+            load_row(y + 1 < y1 ? y + 1 - a.eo : -1, nl1, nl2);
+            accumulate(C, D, e1, e2, true);
+            accumulate(C, D, l1, l2, false);
         }
+        // row prefix: lane-local prefix of its 4 columns, then the lane
+        // offsets in a fixed order (four-wave tiles: wave 0 scans the S1 lane
+        // totals and wave 1 those of S2)
         double pc[4], pd[4];
         pc[0] = C[0]; pc[1] = pc[0] + C[1]; pc[2] = pc[1] + C[2]; pc[3] = pc[2] + C[3];
         pd[0] = D[0]; pd[1] = pd[0] + D[1]; pd[2] = pd[1] + D[2]; pd[3] = pd[2] + D[3];
-        const double sc = wave_scan_f64(pc[3]);
-        const double sd = wave_scan_f64(pd[3]);
-        if (lane == 63) {
-            Tot[0][wave] = sc;
-            Tot[1][wave] = sd;
+        double ec, ed, tc, td;
+        if (NT == 64) {
+            // one wave: its scan gives the offsets and the row total directly
+            const double ic = wave_scan_f64(pc[3]), id = wave_scan_f64(pd[3]);
+            ec = ic - pc[3];
+            ed = id - pd[3];
+            tc = lane_f64(ic, 63);
+            td = lane_f64(id, 63);
+        } else {
+            Tl[0][tid] = pc[3];
+            Tl[1][tid] = pd[3];
+            __syncthreads();
+            if (wave < 2) {
+                const double *Tw = &Tl[wave][4 * lane];
+                const double v0 = Tw[0], v1 = v0 + Tw[1], v2 = v1 + Tw[2], v3 = v2 + Tw[3];
+                const double inc = wave_scan_f64(v3);
+                const double ex = inc - v3;
+                double *E = &El[wave][4 * lane];
+                E[0] = ex;
+                E[1] = ex + v0;
+                E[2] = ex + v1;
+                E[3] = ex + v2;
+                if (lane == 63) El[wave][NT] = inc;
+            }
+            __syncthreads();
+            ec = El[0][tid];
+            ed = El[1][tid];
+            tc = El[0][NT];
+            td = El[1][NT];
         }
-        __syncthreads();
+        if (NT == 64) __syncthreads();  // the previous row's epilogue read P
         {
-            // offsets of the wave totals (fixed order); lanes past the waves
-            // never feed lanes below them
-            const double wc = row_scan16_f64(lane < SOFT_WAVES ? Tot[0][lane & (SOFT_WAVES - 1)] : 0.0);
-            const double wd = row_scan16_f64(lane < SOFT_WAVES ? Tot[1][lane & (SOFT_WAVES - 1)] : 0.0);
-            const double oc = (wave > 0) ? lane_f64(wc, max(wave - 1, 0)) : 0.0;
-            const double od = (wave > 0) ? lane_f64(wd, max(wave - 1, 0)) : 0.0;
-            const double ec = (sc - pc[3]) + oc, ed = (sd - pd[3]) + od;
             double *p1 = &P[0][SLPAD + 1 + 4 * tid];
             double *p2 = &P[1][SLPAD + 1 + 4 * tid];
 #pragma unroll
@@ -274,7 +369,6 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
                 p2[q] = pd[q] + ed;
             }
             if (wave == SOFT_WAVES - 1) {  // right pad: the tile totals
-                const double tc = lane_f64(wc, SOFT_WAVES - 1), td = lane_f64(wd, SOFT_WAVES - 1);
 #pragma unroll
                 for (int q = 0; q < SRPAD / 64; ++q) {
                     P[0][SLPAD + 1 + SNH + 64 * q + lane] = tc;
@@ -284,56 +378,61 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
         }
         __syncthreads();
 
-        const uint32_t soI = (uint32_t)(4 * (int64_t)y * ld);
-        const uint32_t soF = (uint32_t)(4 * (int64_t)y * W);
+        float rowk = 0.0f, rowR = 0.0f;  // this row's dL/dk and dL/dR / (-k / R^2) terms
         const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
-        const double rnr = 1.0 / (double)nr;
+        const double rnr = recip64(nr);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double S1 = P[0][ai0 + 64 * j] - P[0][bi0 + 64 * j];
             const double S2 = P[1][ai0 + 64 * j] - P[1][bi0 + 64 * j];
-            const float Iv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dI, (int)oe[j], (int)soI, 0));
+            const float Iv = Ivs[j];
             if (PH == ADJ) {
-                const __amdgpu_buffer_rsrc_t ddd = srsrc(a.dd + (int64_t)b * H * W, fld_bytes);
-                const float dv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(ddd, (int)oe[j], (int)soF, 0));
-                const float g = dv + (float)S1 + 2.0f * Iv * (float)S2;
+                const float g = Xvs[j] + (float)S1 + 2.0f * Iv * (float)S2;
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g), srsrc(a.gI + (int64_t)b * H * ld, img_bytes),
                                                       (int)oe[j], (int)soI, 2);
                 continue;
             }
-            // the threshold and z in binary64 (z decides delta, which every
-            // gradient scales), the sigmoid and what follows in float32
-            const double rn64 = rnr * rnc[j];
-            const double n = (double)nr * ncd[j];
-            const double m64 = S1 * rn64;
-            const double vn = __builtin_fma(n, S2, -(S1 * S1));
-            const double s64 = vn > 0.0 ? __builtin_sqrt(vn) * rn64 : 0.0;
-            const double q64 = __builtin_fma(s64, rR64, -1.0);     // s/R - 1
-            const double t64 = m64 * __builtin_fma(kb64, q64, 1.0);
-            const float z = (float)(((double)Iv - t64) * rtau64);
-            // sigmoid through e^-|z| <= 1: y and y (1 - y) = e / (1 + e)^2
-            // keep their relative accuracy at both tails
-            const float ea = __expf(-fabsf(z));
-            const float rr = 1.0f / (1.0f + ea);
-            const float yv = (z >= 0.0f ? 1.0f : ea) * rr;
             if (PH == FWD) {
+                // y needs t to about 1e-4: float32 from the binary64 sums on
+                // (n S2 - S1^2 is formed in binary64 against cancellation)
+                const float rnf = (float)(rnr * rnc[j]);
+                const float m = (float)S1 * rnf;
+                const float vf = (float)__builtin_fma((double)nr * ncd[j], S2, -(S1 * S1));
+                const float s = vf > 0.0f ? __builtin_amdgcn_sqrtf(vf) * rnf : 0.0f;
+                const float t = m * __builtin_fmaf(kb, __builtin_fmaf(s, rRf, -1.0f), 1.0f);
+                const float z = (Iv - t) * rtau;
+                const float ea = __expf(-fabsf(z));
+                const float yv = (z >= 0.0f ? 1.0f : ea) * __builtin_amdgcn_rcpf(1.0f + ea);
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(yv), srsrc(a.y + (int64_t)b * H * ld, img_bytes),
                                                       (int)oe[j], (int)soI, 2);
                 continue;
             }
-            const float gv = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                srsrc(a.gy + (int64_t)b * H * ld, img_bytes), (int)oe[j], (int)soI, 0));
-            const float delta = gv * (ea * rr * rr);
+            // the gradients: the threshold and z in binary64 (z decides
+            // delta, which every gradient scales), the sigmoid and what
+            // follows in float32
+            const double rn64 = rnr * rnc[j];
+            const double n = (double)nr * ncd[j];
+            const double m64 = S1 * rn64;
+            const double vn = __builtin_fma(n, S2, -(S1 * S1));
+            const double s64 = sqrt_pos(vn) * rn64;
+            const double q64 = __builtin_fma(s64, rR64, -1.0);     // s/R - 1
+            const double t64 = __builtin_fma(m64 * kb64, q64, m64);
+            const float z = (float)((double)Iv - t64) * rtau;
+            // sigmoid through e^-|z| <= 1: y and y (1 - y) = e / (1 + e)^2
+            // keep their relative accuracy at both tails
+            const float ea = __expf(-fabsf(z));
+            const float rr = __builtin_amdgcn_rcpf(1.0f + ea);
+            const float delta = Xvs[j] * (ea * rr * rr);
             const float e = -delta * rtau;
-            const bool in = oe[j] != SOFF_OUT;
-            dk_acc += in ? (double)e * (m64 * q64) : 0.0;
-            dR_acc += in ? (double)e * (m64 * s64 * cR64) : 0.0;
+            // columns outside the tile read gy = 0, so e = 0 there
+            rowk = __builtin_fmaf(e, (float)(m64 * q64), rowk);
+            rowR = __builtin_fmaf(e, (float)(m64 * s64), rowR);
             const float m = (float)m64, s = (float)s64, q = (float)q64, rn = (float)rn64;
             const float aa = e * __builtin_fmaf(kb, q, 1.0f);
             const float beta = e * kR * m;
             float g1, g2;
             if (s > 0.0f) {
-                const float rns = rn / s;
+                const float rns = rn * __builtin_amdgcn_rcpf(s);
                 g1 = aa * rn - beta * m * rns;
                 g2 = 0.5f * beta * rns;
             } else {
@@ -346,6 +445,10 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g1), f1, (int)oe[j], (int)soF, 0);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g2), f2, (int)oe[j], (int)soF, 0);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(delta * rtau), f3, (int)oe[j], (int)soF, 0);
+        }
+        if (PH == BWD1) {
+            dk_acc += (double)rowk;
+            dR_acc += (double)rowR * cR64;
         }
     }
     if (PH == BWD1) {
@@ -367,40 +470,62 @@ __global__ __launch_bounds__(SOFT_THREADS) void k_soft(SoftArgs a)
     }
 }
 
-// gk[b] = sum of image b's partials, gR = sum of all, each in a fixed order.
-__global__ __launch_bounds__(64) void k_soft_reduce(const double *part, int B, int per_img,
-                                                    float *gk, float *gR)
+// gk[b] = sum of image b's partials, gR = sum of all, each in a fixed order
+// (lane-strided sums, then a fixed wave scan), so repeated runs agree.
+constexpr int REDUCE_THREADS = 256;
+__global__ __launch_bounds__(REDUCE_THREADS) void k_soft_reduce(const double *part, int B, int per_img,
+                                                                float *gk, float *gR)
 {
-    const int t = threadIdx.x;
-    for (int b = t; b < B; b += 64) {
+    __shared__ double wsum[REDUCE_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int b = wave; b < B; b += REDUCE_THREADS / 64) {
         double s = 0.0;
-        for (int i = 0; i < per_img; ++i) s += part[2 * ((int64_t)b * per_img + i)];
-        gk[b] = (float)s;
+        for (int i = lane; i < per_img; i += 64) s += part[2 * ((int64_t)b * per_img + i)];
+        s = lane_f64(wave_scan_f64(s), 63);
+        if (lane == 0) gk[b] = (float)s;
     }
-    if (t == 0) {
-        double s = 0.0;
-        for (int64_t i = 0; i < (int64_t)B * per_img; ++i) s += part[2 * i + 1];
-        gR[0] = (float)s;
+    double s = 0.0;
+    const int64_t total = (int64_t)B * per_img;
+    for (int64_t i = tid; i < total; i += REDUCE_THREADS) s += part[2 * i + 1];
+    s = lane_f64(wave_scan_f64(s), 63);
+    if (lane == 0) wsum[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double r = 0.0;
+        for (int w = 0; w < REDUCE_THREADS / 64; ++w) r += wsum[w];
+        gR[0] = (float)r;
     }
 }
 
-// Tiling shared by the three phases: one column tile when W fits a block,
-// else tiles with a halo wide enough for either window orientation.
+// Tiling shared by the three phases: a single-wave tile when the row and
+// the window fit one, else four-wave tiles: one column tile when W fits,
+// else balanced tiles with a halo wide enough for either window orientation.
 void plan_soft(SoftArgs &a)
 {
     a.o = (a.h + 1) / 2;
     a.u = a.h / 2;
     a.l = (a.w + 1) / 2;
     a.r = a.w / 2;
-    if (a.W <= SNH) {
+    const int lmax = (a.l > a.r + 1) ? a.l : a.r + 1;   // forward l or adjoint r+1
+    const int rmax = (a.r > a.l - 1) ? a.r : a.l - 1;   // forward r or adjoint l-1
+    const int halo = ((lmax - 1) + 3) & ~3;
+    constexpr int SN1 = SoftTile<WAVE_THREADS>::SNH, SN4 = SoftTile<WIDE_THREADS>::SNH;
+    if (a.W <= SN1 && lmax <= SoftTile<WAVE_THREADS>::LPAD - 2 && rmax <= SoftTile<WAVE_THREADS>::RPAD) {
+        a.nt = WAVE_THREADS;
+        a.tile_w = a.W;
+        a.ntx = 1;
+        a.halo_l = 0;
+    } else if (a.W <= SN4) {
+        a.nt = WIDE_THREADS;
         a.tile_w = a.W;
         a.ntx = 1;
         a.halo_l = 0;
     } else {
-        const int lmax = (a.l > a.r + 1) ? a.l : a.r + 1;   // forward l or adjoint r+1
-        const int rmax = (a.r > a.l - 1) ? a.r : a.l - 1;   // forward r or adjoint l-1
-        a.halo_l = ((lmax - 1) + 3) & ~3;
-        a.tile_w = (SNH - a.halo_l - rmax) & ~3;
+        a.nt = WIDE_THREADS;
+        a.halo_l = halo;
+        const int tile4 = (SN4 - halo - rmax) & ~3;
+        a.ntx = (a.W + tile4 - 1) / tile4;
+        a.tile_w = ((a.W + a.ntx - 1) / a.ntx + 3) & ~3;
         a.ntx = (a.W + a.tile_w - 1) / a.tile_w;
     }
     // strips depend on the image geometry only, so an image gives the same
@@ -418,17 +543,22 @@ size_t soft_fields_bytes(int B, int H, int W) { return (size_t)B * H * W * sizeo
 template <int PH>
 void launch_phase(const SoftArgs &a, int blocks, hipStream_t st)
 {
-    if (a.vec) hipLaunchKernelGGL((k_soft<PH, true>), dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
-    else hipLaunchKernelGGL((k_soft<PH, false>), dim3(blocks), dim3(SOFT_THREADS), 0, st, a);
+    if (a.nt == WAVE_THREADS) {
+        if (a.vec) hipLaunchKernelGGL((k_soft<PH, true, WAVE_THREADS>), dim3(blocks), dim3(WAVE_THREADS), 0, st, a);
+        else hipLaunchKernelGGL((k_soft<PH, false, WAVE_THREADS>), dim3(blocks), dim3(WAVE_THREADS), 0, st, a);
+    } else {
+        if (a.vec) hipLaunchKernelGGL((k_soft<PH, true, WIDE_THREADS>), dim3(blocks), dim3(WIDE_THREADS), 0, st, a);
+        else hipLaunchKernelGGL((k_soft<PH, false, WIDE_THREADS>), dim3(blocks), dim3(WIDE_THREADS), 0, st, a);
+    }
 }
 
 }  // namespace
 
 size_t soft_workspace_bytes(int B, int H, int W)
 {
-    // one partial pair per workgroup: column tiles are at least
-    // 1024 - 2 * 128 columns wide (windows up to 257) and strips at least 8
-    // rows tall (or the whole image)
+    // one partial pair per workgroup: column tiles are the whole row or at
+    // least 1024 - 2 * 128 columns wide (windows up to 257), and strips at
+    // least 8 rows tall (or the whole image)
     const size_t tiles = (size_t)B * ((W + 767) / 768) * (size_t)((H + 7) / 8);
     const size_t parts = tiles * 2 * sizeof(double);
     return 3 * ((soft_fields_bytes(B, H, W) + 255) & ~(size_t)255) + ((parts + 255) & ~(size_t)255);
@@ -503,7 +633,7 @@ hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W,
     launch_phase<ADJ>(a, blocks, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(64), 0, st, (const double *)a.part, B, per_img,
+    hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(REDUCE_THREADS), 0, st, (const double *)a.part, B, per_img,
                        gk, gR);
     return hipGetLastError();
 }
