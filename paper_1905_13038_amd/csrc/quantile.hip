@@ -1,15 +1,25 @@
 // Windowed quantiles from sliding 256-bin gray-level histograms (Section 3.4).
 //
-// A workgroup is one wavefront; lane t owns column x0 + t and slides its
-// window histogram DOWN a strip of rows: per row it adds the w gray levels of
-// the entering row and removes those of the leaving row (the Theta(max{h,w})
-// per-pixel cost the paper states).  Histograms are private per lane and live
-// in LDS with the bin index as the major dimension (bin b of lane t at word
-// b * 64 + t), so each lane always hits its own bank.  Bin updates are
-// fire-and-forget LDS atomics.  The quantile is tracked incrementally: the
-// lane keeps its current answer Q and lt = #{window values < Q}, adjusts lt
-// as values enter and leave, then walks Q up or down until
-// lt < rho <= lt + hist[Q].
+// A workgroup is one wavefront; lane t owns output column x0 + t and slides
+// its window histogram DOWN a strip of rows: per row it adds the w gray
+// levels of the entering row and removes those of the leaving row (the
+// Theta(max{h,w}) per-pixel cost the paper states).
+//
+// Histograms are private per lane and live in LDS with the bin as the major
+// dimension, so each lane always hits its own bank.  When no count can
+// exceed 65535 (h w <= 65535) two adjacent bins share a 32-bit word (bin v
+// in half v & 1 of word v >> 1: 32 KB per wave, five waves per CU);
+// otherwise each bin has a word (64 KB per wave).  Bin updates are
+// fire-and-forget LDS atomics.
+//
+// Row data: the wave loads the bytes its 64 windows need from a row (at most
+// 64 + w - 1 of them) as aligned dwords, one or two per lane, prefetched a
+// row ahead; a lane takes its bytes four at a time from the lanes holding
+// them (ds_bpermute) with a byte funnel shift.
+//
+// The quantile is tracked incrementally: the lane keeps its current answer Q
+// and lt = #{window values < Q}, adjusts lt as values enter and leave, then
+// walks Q down or up until lt < rho <= lt + hist[Q].
 #include "internal.hpp"
 
 #include <math.h>
@@ -26,84 +36,316 @@ __device__ __forceinline__ int xcd_remap_q(int b, int n)
     return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
 }
 
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t qrsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// The bytes of one row the wave needs, [cs, cs + nb), held as aligned dwords
+// from the dword containing byte cs: lane t holds dwords t and 64 + t.
+// sh = offset of byte cs in its dword.  Bytes past the row read as zero or
+// as the next row's (never used: lanes only take bytes of their windows).
+template <bool TWO>
+struct RowBytes {
+    uint32_t d0 = 0, d1 = 0;
+    int sh = 0;
+    __device__ __forceinline__ void load(const uint8_t *rowp, int nb, int lane)
+    {
+        const uintptr_t p = (uintptr_t)rowp;
+        const uint8_t *ap = (const uint8_t *)(p & ~(uintptr_t)3);
+        sh = (int)(p & 3);
+        // whole dwords only: a dword crossing the descriptor end reads zero,
+        // and the aligned dword holding the last byte is readable memory
+        const uint32_t bytes = (uint32_t)((sh + nb + 3) & ~3);
+        const __amdgpu_buffer_rsrc_t d = qrsrc(ap, bytes);
+        d0 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane, 0, 0);
+        d1 = TWO ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane + 256, 0, 0) : 0u;
+    }
+    // dword i (0 <= i < 128) of the row's span
+    __device__ __forceinline__ uint32_t dword(int i) const
+    {
+        const int a = (i & 63) << 2;
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)d0);
+        if (!TWO) return v0;
+        const uint32_t v1 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)d1);
+        return i < 64 ? v0 : v1;
+    }
+};
+
+template <bool PACK>
+__device__ __forceinline__ uint32_t bin_word(uint32_t v) { return PACK ? (v >> 1) : v; }
+template <bool PACK>
+__device__ __forceinline__ uint32_t bin_inc(uint32_t v) { return PACK ? ((v & 1u) ? 65536u : 1u) : 1u; }
+template <bool PACK>
+__device__ __forceinline__ int bin_count(const uint32_t *hb, int g)
+{
+    const uint32_t wd = hb[(uint32_t)bin_word<PACK>((uint32_t)g) * QLANES];
+    return PACK ? (int)((wd >> ((g & 1) * 16)) & 0xffffu) : (int)wd;
+}
+
+// LDS word of byte q of val in the lane's histogram, as a byte offset from
+// the histogram base (lane4 = 4 lane), and the increment of its bin.
+template <bool PACK>
+__device__ __forceinline__ void bin_slot(uint32_t val, int q, uint32_t lane4, uint32_t &off, uint32_t &inc)
+{
+    if (PACK) {
+        // word v >> 1 (offset (v >> 1) * 256 + lane4): bits 1..7 of the byte at bits 8..14
+        const uint32_t sh = (q == 0) ? (val << 7) : (val >> (8 * q - 7));
+        off = (sh & 0x7f00u) | lane4;
+        inc = __builtin_amdgcn_ubfe(val, 8 * q, 1) * 65535u + 1u;
+    } else {
+        const uint32_t sh = (q == 0) ? (val << 8) : (q == 1 ? val : (val >> (8 * q - 8)));
+        off = (sh & 0xff00u) | lane4;  // word v at offset v * 256 + lane4
+        inc = 1u;
+    }
+}
+
+template <int SIGN>
+__device__ __forceinline__ void lds_add(uint32_t *hist, uint32_t off, uint32_t inc)
+{
+    uint32_t *p = (uint32_t *)((char *)hist + off);
+    if (SIGN > 0) atomicAdd(p, inc);
+    else atomicSub(p, inc);
+}
+
+// Number of the four bytes of val that are >= Q, in two 8-bit fields (bits
+// 8..15 and 24..31): with K = 0x01000100 - Q (0x00010001), each 16-bit half
+// of (byte + K) carries into its bit 8 exactly when byte >= Q.
+__device__ __forceinline__ uint32_t ge_fields(uint32_t val, uint32_t K)
+{
+    const uint32_t ev = val & 0x00ff00ffu, od = (val >> 8) & 0x00ff00ffu;
+    return ((ev + K) & 0x01000100u) + ((od + K) & 0x01000100u);
+}
+
+constexpr int GROUP = 8;  // dwords of row bytes per group (32 window columns)
+
+// The updates of one group: the window columns kbase .. kbase + 4 GROUP - 1
+// of the lane, from GROUP + 1 dwords of each row span (funnel-shifted by the
+// span's byte offset).  FULL: every column is inside every lane's window and
+// both rows exist, so no byte needs a check, and lt is updated from the
+// group's byte counts; otherwise each byte is checked (a byte outside adds
+// zero) and compared.  BOTH false: only e is added, to the first window,
+// built with Q = 0 (no value lies below it).
+template <bool PACK, bool FULL, bool BOTH>
+__device__ __forceinline__ void group_update(uint32_t *hist, uint32_t lane4, const uint32_t *de, const uint32_t *dl,
+                                             int se, int sl, bool has_e, bool has_l, int kbase, int wmax, int nc,
+                                             int Q, int &lt)
+{
+    const uint32_t K = 0x01000100u - (uint32_t)Q * 0x00010001u;
+    uint32_t ge_e = 0, ge_l = 0;
+#pragma unroll
+    for (int t = 0; t < GROUP; ++t) {
+        const uint32_t ve = __builtin_amdgcn_alignbyte(de[t + 1], de[t], se);
+        const uint32_t vl = BOTH ? __builtin_amdgcn_alignbyte(dl[t + 1], dl[t], sl) : 0u;
+        if (FULL && BOTH) {
+            ge_e += ge_fields(ve, K);
+            ge_l += ge_fields(vl, K);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = kbase + 4 * t + q;
+            const bool ok = FULL || (c < wmax && c < nc);
+            uint32_t off, inc;
+            bin_slot<PACK>(ve, q, lane4, off, inc);
+            const bool oke = FULL || (ok && has_e);
+            lds_add<1>(hist, off, oke ? inc : 0u);
+            if (BOTH) {
+                const bool okl = FULL || (ok && has_l);
+                bin_slot<PACK>(vl, q, lane4, off, inc);
+                lds_add<-1>(hist, off, okl ? inc : 0u);
+                if (!FULL) {
+                    const uint32_t v_e = (ve >> (8 * q)) & 0xffu, v_l = (vl >> (8 * q)) & 0xffu;
+                    lt += (int)(oke && v_e < (uint32_t)Q) - (int)(okl && v_l < (uint32_t)Q);
+                }
+            }
+        }
+    }
+    if (FULL && BOTH) {
+        // bytes below Q: entering minus leaving = (32 - ge_e) - (32 - ge_l)
+        lt += (int)(((ge_l >> 8) & 0xffu) + (ge_l >> 24)) - (int)(((ge_e >> 8) & 0xffu) + (ge_e >> 24));
+    }
+}
+
+// The row step of the lane's histogram: the bytes [rel, rel + nc) of the
+// entering row span e are added and those of the leaving row span l
+// removed (has_e / has_l false: that row lies outside the image).  All
+// ds_bpermutes of a group are issued together, so the LDS round trips are
+// per group, not per dword.  clip: some lane's window is clipped by the
+// image border (nc < w).  BOTH false: only e is added (the first window).
+template <bool PACK, bool TWO, bool BOTH>
+__device__ __forceinline__ void slide_rows(uint32_t *hist, uint32_t lane4, const RowBytes<TWO> &e, const RowBytes<TWO> &l, bool has_e,
+                                           bool has_l, int rel, int nc, int wmax, bool clip, int Q, int &lt)
+{
+    const int be = e.sh + rel, bl = l.sh + rel;
+    const int se = be & 3, sl = bl & 3;
+    const int ie = be >> 2, il = bl >> 2;
+    const bool fast = has_e && (has_l || !BOTH) && !clip;
+    for (int k = 0; k < wmax; k += 4 * GROUP) {
+        // dword indices past the lane's bytes wrap or read the other half:
+        // those bytes are never counted
+        uint32_t de[GROUP + 1], dl[GROUP + 1];
+#pragma unroll
+        for (int t = 0; t <= GROUP; ++t) {
+            de[t] = e.dword(ie + k / 4 + t);
+            dl[t] = BOTH ? l.dword(il + k / 4 + t) : 0u;
+        }
+        if (fast && k + 4 * GROUP <= wmax)
+            group_update<PACK, true, BOTH>(hist, lane4, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+        else
+            group_update<PACK, false, BOTH>(hist, lane4, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+    }
+}
+
+// Walk Q to the rho-th smallest window value: down while lt >= rho, up while
+// lt + hist[Q] < rho (Q stays in [0, 255] whatever the counts hold).  Each
+// LDS round trip reads WALK_WORDS words (16 bins when packed), issued
+// together; a quantile that jumps across an edge then costs a few round
+// trips instead of one per bin.
+constexpr int WALK_WORDS = 8;
+template <bool PACK>
+__device__ __forceinline__ void walk(const uint32_t *hb, int64_t rho, int &Q, int &lt)
+{
+    constexpr int BPW = PACK ? 2 : 1;  // bins per word
+    constexpr int NWORDS = 256 / BPW;
+    while (lt >= rho && Q > 0) {
+        // the word of bin Q-1 and the WALK_WORDS-1 words below it
+        const int w0 = (Q - 1) / BPW;
+        const int lowest = (w0 - WALK_WORDS + 1 > 0 ? w0 - WALK_WORDS + 1 : 0) * BPW;
+        uint32_t wd[WALK_WORDS];
+#pragma unroll
+        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = (w0 - t >= 0) ? hb[(w0 - t) * QLANES] : 0u;
+#pragma unroll
+        for (int t = 0; t < WALK_WORDS; ++t) {
+#pragma unroll
+            for (int hi = BPW - 1; hi >= 0; --hi) {
+                const int g = (w0 - t) * BPW + hi;
+                if (g == Q - 1 && g >= lowest && lt >= rho) {
+                    lt -= PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
+                    Q = g;
+                }
+            }
+        }
+    }
+    while (Q < 255) {
+        // the word of bin Q and the WALK_WORDS-1 words above it
+        const int w0 = Q / BPW;
+        uint32_t wd[WALK_WORDS];
+#pragma unroll
+        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = (w0 + t < NWORDS) ? hb[(w0 + t) * QLANES] : 0u;
+        bool found = false;
+#pragma unroll
+        for (int t = 0; t < WALK_WORDS; ++t) {
+#pragma unroll
+            for (int hi = 0; hi < BPW; ++hi) {
+                const int g = (w0 + t) * BPW + hi;
+                if (!found && g >= Q) {
+                    if (g == 255) {
+                        Q = 255;
+                        found = true;
+                    } else {
+                        const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
+                        if (lt + cnt >= rho) {
+                            Q = g;
+                            found = true;
+                        } else {
+                            lt += cnt;
+                        }
+                    }
+                }
+            }
+        }
+        if (found) break;
+        Q = (w0 + WALK_WORDS) * BPW;
+    }
+}
+
+template <bool PACK, bool TWO>
 __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int nsy)
 {
-    extern __shared__ uint32_t hist[];  // [256][QLANES]
+    extern __shared__ uint32_t hist[];  // [PACK ? 128 : 256][QLANES] words
+    constexpr int NW = PACK ? 128 : 256;
     const int lane = threadIdx.x;
     const int L = xcd_remap_q(blockIdx.x, gridDim.x);
     const int tx = L / nsy;
     const int sy = L - tx * nsy;
-    const int j = tx * QLANES + lane;
+    const int x0 = tx * QLANES;
+    const int j = x0 + lane;
     const bool active = j < a.W;
     const int y0 = sy * seg;
     const int y1 = min(y0 + seg, a.H);
     const int H = a.H, W = a.W;
 
     uint32_t *hb = hist + lane;
+    const uint32_t lane4 = 4u * (uint32_t)lane;
 #pragma unroll 8
-    for (int b = 0; b < 256; ++b) hb[b * QLANES] = 0u;
+    for (int b = 0; b < NW; ++b) hb[b * QLANES] = 0u;
 
-    // clipped window columns of this lane
+    // bytes any lane of the wave needs: columns cs .. ce
+    const int cs = max(x0 - a.l + 1, 0);
+    const int ce = min(x0 + QLANES - 1 + a.r, W - 1);
+    const int nb = ce - cs + 1;
+    // clipped window columns of this lane, relative to cs
     const int c0 = max(j - a.l + 1, 0);
     const int c1 = active ? min(j + a.r, W - 1) : c0 - 1;
-    const int nc = c1 - c0 + 1;
+    const int nc = max(c1 - c0 + 1, 0);
+    const int rel = c0 - cs;
+    const int wmax = a.w;
+    // some window of the wave clipped by the image border (wave-uniform)
+    const bool clip = __builtin_amdgcn_ballot_w64(nc < wmax) != 0;
 
-    // histogram of the window of row y0
-    {
-        const int r0 = max(y0 - a.o + 1, 0), r1 = min(y0 + a.u, H - 1);
-        for (int row = r0; row <= r1; ++row) {
-            const uint8_t *p = a.I + (int64_t)row * a.ldI;
-#pragma unroll 4
-            for (int c = c0; c <= c1; ++c) atomicAdd(&hb[(uint32_t)p[c] * QLANES], 1u);
-        }
-    }
+    auto rowp = [&](int row) { return a.I + (int64_t)row * a.ldI + cs; };
 
     int Q = 0;   // current answer
     int lt = 0;  // number of window values below Q
-    for (int y = y0; y < y1; ++y) {
+    // histogram of the window of row y0
+    {
+        const int r0 = max(y0 - a.o + 1, 0), r1 = min(y0 + a.u, H - 1);
+        RowBytes<TWO> rb;
+        if (r0 <= r1) rb.load(rowp(r0), nb, lane);
+        for (int row = r0; row <= r1; ++row) {
+            RowBytes<TWO> cur = rb;
+            if (row < r1) rb.load(rowp(row + 1), nb, lane);
+            slide_rows<PACK, TWO, false>(hist, lane4, cur, cur, true, false, rel, nc, wmax, clip, Q, lt);
+        }
+    }
+
+    // rows entering and leaving the window of row y: y + u and y - o; with
+    // them the lane's own pixel of row y (for the mask), one row ahead
+    RowBytes<TWO> ne, nl;
+    uint32_t npx = 0;
+    auto load_row = [&](int y) {
         if (y > y0) {
-            const int ra = y + a.u, rb = y - a.o;
-            if (ra < H) {
-                const uint8_t *p = a.I + (int64_t)ra * a.ldI;
-#pragma unroll 4
-                for (int c = c0; c <= c1; ++c) {
-                    const uint32_t v = p[c];
-                    atomicAdd(&hb[v * QLANES], 1u);
-                    lt += (int)(v < (uint32_t)Q);
-                }
-            }
-            if (rb >= 0) {
-                const uint8_t *p = a.I + (int64_t)rb * a.ldI;
-#pragma unroll 4
-                for (int c = c0; c <= c1; ++c) {
-                    const uint32_t v = p[c];
-                    atomicSub(&hb[v * QLANES], 1u);
-                    lt -= (int)(v < (uint32_t)Q);
-                }
-            }
+            if (y + a.u < H) ne.load(rowp(y + a.u), nb, lane);
+            if (y - a.o >= 0) nl.load(rowp(y - a.o), nb, lane);
+        }
+        const __amdgpu_buffer_rsrc_t d = qrsrc(a.I + (int64_t)y * a.ldI + x0, (uint32_t)(W - x0));
+        npx = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, lane, 0, 0);
+    };
+    load_row(y0);
+    for (int y = y0; y < y1; ++y) {
+        const RowBytes<TWO> e = ne, l = nl;
+        const uint32_t iv = npx;
+        if (y + 1 < y1) load_row(y + 1);
+        if (y > y0) {
+            const bool has_e = y + a.u < H, has_l = y - a.o >= 0;
+            slide_rows<PACK, TWO, true>(hist, lane4, e, l, has_e, has_l, rel, nc, wmax, clip, Q, lt);
         }
         if (!active) continue;
         const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
         const int64_t n = (int64_t)nr * nc;
         int64_t rho = (int64_t)ceil(a.q * (double)n);
         if (rho < 1) rho = 1;
-        // walk down while too many values lie below Q
-        // (the bounds on Q keep both walks finite whatever the counts hold)
-        while (lt >= rho && Q > 0) {
-            --Q;
-            lt -= (int)hb[Q * QLANES];
-        }
-        // walk up while the values up to Q are still fewer than rho
-        while (Q < 255) {
-            const int hq = (int)hb[Q * QLANES];
-            if (lt + hq >= rho) break;
-            lt += hq;
-            ++Q;
-        }
-        const uint8_t iv = a.I[(int64_t)y * a.ldI + j];
+        walk<PACK>(hb, rho, Q, lt);
         a.Q[(int64_t)y * a.ldQ + j] = (uint8_t)Q;
-        if (a.mask) a.mask[(int64_t)y * a.ldM + j] = (iv < (uint8_t)Q) ? 1 : 0;
+        if (a.mask) a.mask[(int64_t)y * a.ldM + j] = (iv < (uint32_t)Q) ? 1 : 0;
     }
+}
+
+template <bool PACK, bool TWO>
+void launch_variant(const QuantJob &a, int blocks, int seg, int nsy, hipStream_t stream)
+{
+    const size_t lds = (PACK ? 128 : 256) * QLANES * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_quantile<PACK, TWO>), dim3(blocks), dim3(QLANES), lds, stream, a, seg, nsy);
 }
 
 }  // namespace
@@ -111,15 +353,26 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
 hipError_t launch_quantile(const QuantJob &a, hipStream_t stream)
 {
     const int ntx = (a.W + QLANES - 1) / QLANES;
-    // strips long enough that building the first window (h*w updates) stays
-    // small next to the 2w updates per row of the slide
-    int seg = (int)(((long)a.H * ntx + 511) / 512);
-    if (seg < 2 * a.h) seg = 2 * a.h;
+    // strips: at least h/2 rows (building the first window costs h w
+    // updates against 2 w per row of the slide), more when that still
+    // leaves about five waves per CU
+    int seg = (int)(((long)a.H * ntx + 1279) / 1280);
+    if (seg < (a.h + 1) / 2) seg = (a.h + 1) / 2;
     if (seg < 8) seg = 8;
     if (seg > a.H) seg = a.H;
     const int nsy = (a.H + seg - 1) / seg;
-    const size_t lds = 256 * QLANES * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_quantile, dim3(ntx * nsy), dim3(QLANES), lds, stream, a, seg, nsy);
+    const bool pack = (int64_t)a.h * a.w <= 65535;
+    // dwords a lane reads from the row span: from (sh + rel) / 4 <= 16 to
+    // 16 + (w - 1) / 4 + 1; one dword per lane holds dwords 0 .. 63
+    const bool two = 16 + (a.w - 1) / 4 + 1 >= QLANES;
+    const int blocks = ntx * nsy;
+    if (pack) {
+        if (two) launch_variant<true, true>(a, blocks, seg, nsy, stream);
+        else launch_variant<true, false>(a, blocks, seg, nsy, stream);
+    } else {
+        if (two) launch_variant<false, true>(a, blocks, seg, nsy, stream);
+        else launch_variant<false, false>(a, blocks, seg, nsy, stream);
+    }
     return hipGetLastError();
 }
 
