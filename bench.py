@@ -8,10 +8,10 @@ and standard deviation (10 bytes of algorithmic HBM traffic per pixel).
 
 Prints ONE JSON line.  `value` is Gpix/s over the K timed steps (inputs
 resident in HBM; buffer sets rotated so the 256 MB Infinity Cache cannot serve
-repeats).  `roofline` prices the kernel's average duration (HIP events around the
-K timed launches, on the stream the kernel runs on) against the 8 TB/s HBM
-peak; `traffic` is the counter-derived HBM bytes per launch from the
-committed profile summary, or null when that was taken on other kernel
+repeats).  `roofline` prices the kernel's average duration (HIP events around
+graph replays of the same launches, on the stream they run on) against the
+8 TB/s HBM peak; `traffic` is the counter-derived HBM bytes per launch from
+the committed profile summary, or null when that was taken on other kernel
 source.
 `cpu_baseline` times the CPU oracle (Algorithm 1 sweep plus the binary64
 threshold, one thread) on the same page.
