@@ -239,6 +239,8 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
     const int bi0 = SLPAD + ec0 - a.el - xh + 1;  // prefix index of j - el
     uint32_t oe[4];  // byte offset of the column in a row, 2^31 outside the tile
     double ncd[4], rnc[4];  // forward column counts and their reciprocals
+    float rnf[4] = {0, 0, 0, 0};  // FWD: float32 1/n of the current row count
+    int nr_prev = -1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int c = ec0 + 64 * j;
@@ -381,6 +383,11 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
         float rowk = 0.0f, rowR = 0.0f;  // this row's dL/dk and dL/dR / (-k / R^2) terms
         const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
         const double rnr = recip64(nr);
+        if (PH == FWD && nr != nr_prev) {  // row counts change only near the image's top and bottom
+            nr_prev = nr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rnf[j] = (float)(rnr * rnc[j]);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const double S1 = P[0][ai0 + 64 * j] - P[0][bi0 + 64 * j];
@@ -395,10 +402,9 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
             if (PH == FWD) {
                 // y needs t to about 1e-4: float32 from the binary64 sums on
                 // (n S2 - S1^2 is formed in binary64 against cancellation)
-                const float rnf = (float)(rnr * rnc[j]);
-                const float m = (float)S1 * rnf;
+                const float m = (float)S1 * rnf[j];
                 const float vf = (float)__builtin_fma((double)nr * ncd[j], S2, -(S1 * S1));
-                const float s = vf > 0.0f ? __builtin_amdgcn_sqrtf(vf) * rnf : 0.0f;
+                const float s = vf > 0.0f ? __builtin_amdgcn_sqrtf(vf) * rnf[j] : 0.0f;
                 const float t = m * __builtin_fmaf(kb, __builtin_fmaf(s, rRf, -1.0f), 1.0f);
                 const float z = (Iv - t) * rtau;
                 const float ea = __expf(-fabsf(z));
@@ -424,21 +430,17 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
             const float rr = __builtin_amdgcn_rcpf(1.0f + ea);
             const float delta = Xvs[j] * (ea * rr * rr);
             const float e = -delta * rtau;
-            // columns outside the tile read gy = 0, so e = 0 there
-            rowk = __builtin_fmaf(e, (float)(m64 * q64), rowk);
-            rowR = __builtin_fmaf(e, (float)(m64 * s64), rowR);
             const float m = (float)m64, s = (float)s64, q = (float)q64, rn = (float)rn64;
+            // columns outside the tile read gy = 0, so e = 0 there
+            const float em = e * m;
+            rowk = __builtin_fmaf(em, q, rowk);
+            rowR = __builtin_fmaf(em, s, rowR);
             const float aa = e * __builtin_fmaf(kb, q, 1.0f);
-            const float beta = e * kR * m;
-            float g1, g2;
-            if (s > 0.0f) {
-                const float rns = rn * __builtin_amdgcn_rcpf(s);
-                g1 = aa * rn - beta * m * rns;
-                g2 = 0.5f * beta * rns;
-            } else {
-                g1 = aa * rn;
-                g2 = 0.0f;
-            }
+            const float beta = em * kR;
+            // 1 / (n s), or 0 where s = 0: the s-terms drop out there
+            const float rns = s > 0.0f ? rn * __builtin_amdgcn_rcpf(s) : 0.0f;
+            const float g1 = __builtin_fmaf(-beta * m, rns, aa * rn);
+            const float g2 = 0.5f * beta * rns;
             const __amdgpu_buffer_rsrc_t f1 = srsrc(a.G1 + (int64_t)b * H * W, fld_bytes);
             const __amdgpu_buffer_rsrc_t f2 = srsrc(a.G2 + (int64_t)b * H * W, fld_bytes);
             const __amdgpu_buffer_rsrc_t f3 = srsrc(a.dd + (int64_t)b * H * W, fld_bytes);

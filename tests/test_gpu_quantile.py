@@ -60,3 +60,17 @@ def test_constant_and_extremes(bz):
         Q, mask = run(bz, J, 7, 6, q)
         rq, rm = oracle.quantile_sort(J, 7, 6, q)
         assert np.array_equal(Q, rq) and np.array_equal(mask, rm)
+
+
+@pytest.mark.parametrize("off,ld", [(1, 203), (3, 256), (2, 201)])
+def test_unaligned_strided(bz, off, ld):
+    # base offsets and row strides that put the row spans at every byte
+    # alignment (the row bytes are read as aligned dwords)
+    H, W = 90, 200
+    buf = np.random.default_rng(off * 1000 + ld).integers(0, 256, size=(H * ld + off + 8,), dtype=np.uint8)
+    d = dev(buf)
+    view = d[off:off + H * ld].view(H, ld)[:, :W]
+    host = np.ascontiguousarray(buf[off:off + H * ld].reshape(H, ld)[:, :W])
+    Q, mask = bz.window_quantile(view, 15, 21, 0.3)
+    rq, rm = oracle.quantile_hist(host, 15, 21, 0.3)
+    assert np.array_equal(Q.cpu().numpy(), rq) and np.array_equal(mask.cpu().numpy(), rm)

@@ -89,3 +89,53 @@ def test_k_zero_R_gradient(bz):
     g = np.random.default_rng(1).standard_normal(I.shape)
     _, _, _, gR = run(bz, I, np.zeros(1, np.float32), 128.0, 9, 9, g)
     assert gR == 0.0
+
+
+def test_tall_image_no_drift(bz):
+    # 2000 rows: the binary64 running sums restart with every strip, so the
+    # last rows match the oracle as well as the first
+    I = gen_document(2000, 40, 17, noise=10, stain=True, dtype=np.float32)[None]
+    k = np.array([0.35], np.float32)
+    g = np.random.default_rng(17).standard_normal(I.shape)
+    compare(bz, I, k, 128.0, 31, 31, g)
+
+
+def test_strided_rows_match_contiguous(bz):
+    # row stride ld = W + 3 (no 16-byte row loads) gives the bits of the
+    # contiguous call
+    import ctypes
+    lib = bz.lib
+    B, H, W, ld, h, w, tau = 2, 70, 96, 99, 9, 11, 2.0
+    I = np.stack([gen_document(H, W, 40 + b, noise=10, stain=True, dtype=np.float32) for b in range(B)])
+    g = np.random.default_rng(3).standard_normal((B, H, W)).astype(np.float32)
+    k = torch.tensor([0.3, 0.45], dtype=torch.float32, device="cuda")
+    R = torch.tensor([128.0], dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+
+    def padded(a):
+        p = torch.zeros((B, H, ld), dtype=torch.float32, device="cuda")
+        p[:, :, :W] = torch.from_numpy(a).cuda()
+        return p
+
+    def run_c(Ib, gb, stride):
+        y = torch.full_like(Ib, -7.0)
+        gI = torch.full_like(Ib, -7.0)
+        gk = torch.empty(B, dtype=torch.float32, device="cuda")
+        gR = torch.empty(1, dtype=torch.float32, device="cuda")
+        nb = int(lib.bz_soft_workspace_size(B, H, W))
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        assert lib.bz_soft_sauvola_fwd(Ib.data_ptr(), B, H, W, stride, h, w, k.data_ptr(), R.data_ptr(), tau,
+                                       y.data_ptr(), st) == 0
+        assert lib.bz_soft_sauvola_bwd(Ib.data_ptr(), gb.data_ptr(), B, H, W, stride, h, w, k.data_ptr(),
+                                       R.data_ptr(), tau, gI.data_ptr(), gk.data_ptr(), gR.data_ptr(),
+                                       ws.data_ptr(), nb, st) == 0
+        torch.cuda.synchronize()
+        return y[:, :, :W].cpu().numpy(), gI[:, :, :W].cpu().numpy(), gk.cpu().numpy(), gR.cpu().numpy(), \
+            y[:, :, W:].cpu().numpy(), gI[:, :, W:].cpu().numpy()
+
+    a = run_c(torch.from_numpy(I).cuda(), torch.from_numpy(g).cuda(), W)
+    b = run_c(padded(I), padded(g), ld)
+    for x, z in zip(a[:4], b[:4]):
+        assert np.array_equal(x, z)
+    # the padding columns of the outputs are not written
+    assert np.all(b[4] == -7.0) and np.all(b[5] == -7.0)
