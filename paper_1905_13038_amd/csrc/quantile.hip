@@ -8,7 +8,7 @@
 // Histograms are private per lane and live in LDS with the bin as the major
 // dimension, so each lane always hits its own bank.  When no count can
 // exceed 65535 (h w <= 65535) two adjacent bins share a 32-bit word (bin v
-// in half v & 1 of word v >> 1: 32 KB per wave, five waves per CU);
+// in half v & 1 of word v >> 1: 32 KB per wave, four waves per CU);
 // otherwise each bin has a word (64 KB per wave).  Bin updates are
 // fire-and-forget LDS atomics.
 //
@@ -350,18 +350,32 @@ void launch_variant(const QuantJob &a, int blocks, int seg, int nsy, hipStream_t
 
 }  // namespace
 
+// Waves of histogram size `lds` bytes that stay resident on the device at
+// once.  Measured on MI355X: four 32 KB workgroups fit on a CU but not five
+// (five fit at 31 KB), so the usable LDS per CU is taken as 158 KB.
+static int resident_waves(size_t lds)
+{
+    int device = 0, cus = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int per_cu = (int)((160u * 1024u - 2048u) / lds);
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
 hipError_t launch_quantile(const QuantJob &a, hipStream_t stream)
 {
     const int ntx = (a.W + QLANES - 1) / QLANES;
-    // strips: at least h/2 rows (building the first window costs h w
-    // updates against 2 w per row of the slide), more when that still
-    // leaves about five waves per CU
-    int seg = (int)(((long)a.H * ntx + 1279) / 1280);
+    const bool pack = (int64_t)a.h * a.w <= 65535;
+    // strips: one resident round of waves (a wave more would run in a
+    // second round), and at least h/2 rows (building the first window
+    // costs h w updates against 2 w per row of the slide)
+    const long target = resident_waves((pack ? 128 : 256) * QLANES * sizeof(uint32_t));
+    int seg = (int)(((long)a.H * ntx + target - 1) / target);
     if (seg < (a.h + 1) / 2) seg = (a.h + 1) / 2;
     if (seg < 8) seg = 8;
     if (seg > a.H) seg = a.H;
     const int nsy = (a.H + seg - 1) / seg;
-    const bool pack = (int64_t)a.h * a.w <= 65535;
     // dwords a lane reads from the row span: from (sh + rel) / 4 <= 16 to
     // 16 + (w - 1) / 4 + 1; one dword per lane holds dwords 0 .. 63
     const bool two = 16 + (a.w - 1) / 4 + 1 >= QLANES;
