@@ -84,28 +84,26 @@ __device__ __forceinline__ int bin_count(const uint32_t *hb, int g)
 }
 
 // LDS word of byte q of val in the lane's histogram, as a byte offset from
-// the histogram base (lane4 = 4 lane), and the increment of its bin.
-template <bool PACK>
-__device__ __forceinline__ void bin_slot(uint32_t val, int q, uint32_t lane4, uint32_t &off, uint32_t &inc)
+// the histogram base (lane4 = 4 lane), and the signed increment of its bin:
+// +-(1 + 65535 b) adds one to the low (b = 0) or high half of a packed word
+// (one 24-bit multiply-add).
+template <bool PACK, int q, int SIGN>
+__device__ __forceinline__ void bin_slot(uint32_t val, uint32_t lane4, uint32_t &off, uint32_t &inc)
 {
     if (PACK) {
-        // word v >> 1 (offset (v >> 1) * 256 + lane4): bits 1..7 of the byte at bits 8..14
-        const uint32_t sh = (q == 0) ? (val << 7) : (val >> (8 * q - 7));
-        off = (sh & 0x7f00u) | lane4;
-        inc = __builtin_amdgcn_ubfe(val, 8 * q, 1) * 65535u + 1u;
+        off = (((val >> (8 * q + 1)) & 0x7fu) << 8) | lane4;  // word v >> 1 at (v >> 1) * 256 + lane4
+        const int b = (int)((val >> (8 * q)) & 1u);
+        inc = (uint32_t)(__mul24(b, SIGN * 65535) + SIGN);
     } else {
-        const uint32_t sh = (q == 0) ? (val << 8) : (q == 1 ? val : (val >> (8 * q - 8)));
-        off = (sh & 0xff00u) | lane4;  // word v at offset v * 256 + lane4
-        inc = 1u;
+        off = (((val >> (8 * q)) & 0xffu) << 8) | lane4;  // word v at v * 256 + lane4
+        inc = (uint32_t)SIGN;
     }
 }
 
-template <int SIGN>
+// Adds inc (already signed) to the word at byte offset off.
 __device__ __forceinline__ void lds_add(uint32_t *hist, uint32_t off, uint32_t inc)
 {
-    uint32_t *p = (uint32_t *)((char *)hist + off);
-    if (SIGN > 0) atomicAdd(p, inc);
-    else atomicSub(p, inc);
+    atomicAdd((uint32_t *)((char *)hist + off), inc);
 }
 
 // Number of the four bytes of val that are >= Q, in two 8-bit fields (bits
@@ -113,11 +111,34 @@ __device__ __forceinline__ void lds_add(uint32_t *hist, uint32_t off, uint32_t i
 // of (byte + K) carries into its bit 8 exactly when byte >= Q.
 __device__ __forceinline__ uint32_t ge_fields(uint32_t val, uint32_t K)
 {
-    const uint32_t ev = val & 0x00ff00ffu, od = (val >> 8) & 0x00ff00ffu;
+    const uint32_t ev = val & 0x00ff00ffu;
+    const uint32_t od = __builtin_amdgcn_perm(0u, val, 0x0c030c01u);  // bytes 1, 3 into 0, 2
     return ((ev + K) & 0x01000100u) + ((od + K) & 0x01000100u);
 }
 
 constexpr int GROUP = 8;  // dwords of row bytes per group (32 window columns)
+
+// Byte q of the entering (ve) and leaving (vl) dwords at window column c0 + q.
+template <bool PACK, bool FULL, bool BOTH, int q>
+__device__ __forceinline__ void group_bytes(uint32_t *hist, uint32_t lane4, uint32_t ve, uint32_t vl, bool has_e,
+                                            bool has_l, int c0, int wmax, int nc, int Q, int &lt)
+{
+    const int c = c0 + q;
+    const bool ok = FULL || (c < wmax && c < nc);
+    uint32_t off, inc;
+    bin_slot<PACK, q, 1>(ve, lane4, off, inc);
+    const bool oke = FULL || (ok && has_e);
+    lds_add(hist, off, oke ? inc : 0u);
+    if (BOTH) {
+        const bool okl = FULL || (ok && has_l);
+        bin_slot<PACK, q, -1>(vl, lane4, off, inc);
+        lds_add(hist, off, okl ? inc : 0u);
+        if (!FULL) {
+            const uint32_t v_e = (ve >> (8 * q)) & 0xffu, v_l = (vl >> (8 * q)) & 0xffu;
+            lt += (int)(oke && v_e < (uint32_t)Q) - (int)(okl && v_l < (uint32_t)Q);
+        }
+    }
+}
 
 // The updates of one group: the window columns kbase .. kbase + 4 GROUP - 1
 // of the lane, from GROUP + 1 dwords of each row span (funnel-shifted by the
@@ -141,24 +162,10 @@ __device__ __forceinline__ void group_update(uint32_t *hist, uint32_t lane4, con
             ge_e += ge_fields(ve, K);
             ge_l += ge_fields(vl, K);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = kbase + 4 * t + q;
-            const bool ok = FULL || (c < wmax && c < nc);
-            uint32_t off, inc;
-            bin_slot<PACK>(ve, q, lane4, off, inc);
-            const bool oke = FULL || (ok && has_e);
-            lds_add<1>(hist, off, oke ? inc : 0u);
-            if (BOTH) {
-                const bool okl = FULL || (ok && has_l);
-                bin_slot<PACK>(vl, q, lane4, off, inc);
-                lds_add<-1>(hist, off, okl ? inc : 0u);
-                if (!FULL) {
-                    const uint32_t v_e = (ve >> (8 * q)) & 0xffu, v_l = (vl >> (8 * q)) & 0xffu;
-                    lt += (int)(oke && v_e < (uint32_t)Q) - (int)(okl && v_l < (uint32_t)Q);
-                }
-            }
-        }
+        group_bytes<PACK, FULL, BOTH, 0>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 1>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 2>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 3>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
     }
     if (FULL && BOTH) {
         // bytes below Q: entering minus leaving = (32 - ge_e) - (32 - ge_l)
@@ -203,67 +210,162 @@ __device__ __forceinline__ void slide_rows(uint32_t *hist, uint32_t lane4, const
 // trips instead of one per bin.
 constexpr int WALK_WORDS = 8;
 template <bool PACK>
-__device__ __forceinline__ void walk(const uint32_t *hb, int64_t rho, int &Q, int &lt)
+__device__ __forceinline__ void walk(const uint32_t *hb, int rho, int &Q, int &lt)
 {
     constexpr int BPW = PACK ? 2 : 1;  // bins per word
     constexpr int NWORDS = 256 / BPW;
+    // each step below is a select, so the lanes of a chunk stay converged
     while (lt >= rho && Q > 0) {
         // the word of bin Q-1 and the WALK_WORDS-1 words below it
         const int w0 = (Q - 1) / BPW;
         const int lowest = (w0 - WALK_WORDS + 1 > 0 ? w0 - WALK_WORDS + 1 : 0) * BPW;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
-        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = (w0 - t >= 0) ? hb[(w0 - t) * QLANES] : 0u;
+        for (int t = 0; t < WALK_WORDS; ++t) {
+            const int wi = w0 - t;  // clamped reads: bins below 0 are never stepped to
+            wd[t] = hb[(wi > 0 ? wi : 0) * QLANES];
+        }
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) {
 #pragma unroll
             for (int hi = BPW - 1; hi >= 0; --hi) {
                 const int g = (w0 - t) * BPW + hi;
-                if (g == Q - 1 && g >= lowest && lt >= rho) {
-                    lt -= PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
-                    Q = g;
-                }
+                const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
+                const bool step = g == Q - 1 && g >= lowest && lt >= rho;
+                lt = step ? lt - cnt : lt;
+                Q = step ? g : Q;
             }
         }
     }
-    while (Q < 255) {
+    bool found = Q >= 255;
+    while (!found) {
         // the word of bin Q and the WALK_WORDS-1 words above it
         const int w0 = Q / BPW;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
-        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = (w0 + t < NWORDS) ? hb[(w0 + t) * QLANES] : 0u;
-        bool found = false;
+        for (int t = 0; t < WALK_WORDS; ++t) {
+            const int wi = w0 + t;  // clamped reads: the walk stops at bin 255
+            wd[t] = hb[(wi < NWORDS - 1 ? wi : NWORDS - 1) * QLANES];
+        }
+        const int q0 = Q;
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) {
 #pragma unroll
             for (int hi = 0; hi < BPW; ++hi) {
                 const int g = (w0 + t) * BPW + hi;
-                if (!found && g >= Q) {
-                    if (g == 255) {
-                        Q = 255;
-                        found = true;
-                    } else {
-                        const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
-                        if (lt + cnt >= rho) {
-                            Q = g;
-                            found = true;
-                        } else {
-                            lt += cnt;
-                        }
-                    }
-                }
+                const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
+                const bool live = !found && g >= q0;
+                const bool hit = live && (g >= 255 || lt + cnt >= rho);
+                lt = (live && !hit) ? lt + cnt : lt;
+                Q = hit ? g : Q;
+                found = found || hit;
             }
         }
-        if (found) break;
-        Q = (w0 + WALK_WORDS) * BPW;
+        Q = found ? Q : (w0 + WALK_WORDS) * BPW;
     }
+}
+
+// Software-pipelined row step for windows of at most 4 PGROUP columns.  The
+// walk of row y reads the histogram after row y's atomics; an LDS read waits
+// for every earlier LDS operation of the wave, so the atomics are followed
+// by VALU work that needs no LDS: decoding row y+1 (from bytes fetched
+// before the atomics) into LDS offsets and increments.
+constexpr int PGROUP = 8;
+struct PipeRow {
+    uint32_t off[2][4 * PGROUP], inc[2][4 * PGROUP];  // [entering, leaving] updates
+    uint32_t raw[2][PGROUP];                          // their bytes (255 where not counted)
+};
+
+// The row span dwords of a lane's window bytes: GROUP + 1 per row; se, sl:
+// the byte offsets of the first window byte in its dword.
+template <bool TWO>
+__device__ __forceinline__ void fetch_rows(uint32_t *de, uint32_t *dl, int &se, int &sl, const RowBytes<TWO> &e,
+                                           const RowBytes<TWO> &l, int rel)
+{
+    const int be = e.sh + rel, bl = l.sh + rel;
+    se = be & 3;
+    sl = bl & 3;
+#pragma unroll
+    for (int t = 0; t <= PGROUP; ++t) {
+        de[t] = e.dword((be >> 2) + t);
+        dl[t] = l.dword((bl >> 2) + t);
+    }
+}
+
+template <bool PACK, bool FULL, int q>
+__device__ __forceinline__ void decode_byte(PipeRow &S, int t, uint32_t ve, uint32_t vl, uint32_t me, uint32_t ml,
+                                            uint32_t lane4)
+{
+    uint32_t off, inc;
+    bin_slot<PACK, q, 1>(ve, lane4, off, inc);
+    S.off[0][4 * t + q] = off;
+    S.inc[0][4 * t + q] = (FULL || ((me >> (8 * q)) & 1u) == 0u) ? inc : 0u;
+    bin_slot<PACK, q, -1>(vl, lane4, off, inc);
+    S.off[1][4 * t + q] = off;
+    S.inc[1][4 * t + q] = (FULL || ((ml >> (8 * q)) & 1u) == 0u) ? inc : 0u;
+}
+
+// Offsets and increments of a row's updates.  FULL: all 4 PGROUP columns are
+// in every lane's window and both rows exist; otherwise a byte outside the
+// lane's window (or of a missing row) gets increment 0 and reads as 255,
+// which no rank count takes as below Q.
+template <bool PACK, bool FULL>
+__device__ __forceinline__ void decode_rows(PipeRow &S, const uint32_t *de, const uint32_t *dl, int se, int sl,
+                                            bool has_e, bool has_l, int wmax, int nc, uint32_t lane4)
+{
+#pragma unroll
+    for (int t = 0; t < PGROUP; ++t) {
+        uint32_t ve = __builtin_amdgcn_alignbyte(de[t + 1], de[t], se);
+        uint32_t vl = __builtin_amdgcn_alignbyte(dl[t + 1], dl[t], sl);
+        uint32_t me = 0, ml = 0;
+        if (!FULL) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * t + q;
+                const bool ok = c < wmax && c < nc;
+                me |= (ok && has_e) ? 0u : (0xffu << (8 * q));
+                ml |= (ok && has_l) ? 0u : (0xffu << (8 * q));
+            }
+            ve |= me;
+            vl |= ml;
+        }
+        S.raw[0][t] = ve;
+        S.raw[1][t] = vl;
+        decode_byte<PACK, FULL, 0>(S, t, ve, vl, me, ml, lane4);
+        decode_byte<PACK, FULL, 1>(S, t, ve, vl, me, ml, lane4);
+        decode_byte<PACK, FULL, 2>(S, t, ve, vl, me, ml, lane4);
+        decode_byte<PACK, FULL, 3>(S, t, ve, vl, me, ml, lane4);
+    }
+}
+
+__device__ __forceinline__ void apply_rows(uint32_t *hist, const PipeRow &S)
+{
+#pragma unroll
+    for (int i = 0; i < 4 * PGROUP; ++i) {
+        lds_add(hist, S.off[0][i], S.inc[0][i]);
+        lds_add(hist, S.off[1][i], S.inc[1][i]);
+    }
+}
+
+// lt += (entering bytes below Q) - (leaving bytes below Q); bytes not
+// counted read 255 in both rows.
+__device__ __forceinline__ void count_below(const PipeRow &S, int Q, int &lt)
+{
+    const uint32_t K = 0x01000100u - (uint32_t)Q * 0x00010001u;
+    uint32_t ge_e = 0, ge_l = 0;
+#pragma unroll
+    for (int t = 0; t < PGROUP; ++t) {
+        ge_e += ge_fields(S.raw[0][t], K);
+        ge_l += ge_fields(S.raw[1][t], K);
+    }
+    lt += (int)(((ge_l >> 8) & 0xffu) + (ge_l >> 24)) - (int)(((ge_e >> 8) & 0xffu) + (ge_e >> 24));
 }
 
 template <bool PACK, bool TWO>
 __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int nsy)
 {
-    extern __shared__ uint32_t hist[];  // [PACK ? 128 : 256][QLANES] words
     constexpr int NW = PACK ? 128 : 256;
+    __shared__ uint32_t hist[NW * QLANES];  // [NW][QLANES] words: bin-major, lane-minor
     const int lane = threadIdx.x;
     const int L = xcd_remap_q(blockIdx.x, gridDim.x);
     const int tx = L / nsy;
@@ -309,6 +411,71 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
         }
     }
 
+    auto pixel = [&](int y) {  // the lane's own pixel of row y (for the mask)
+        const __amdgpu_buffer_rsrc_t d = qrsrc(a.I + (int64_t)y * a.ldI + x0, (uint32_t)(W - x0));
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, lane, 0, 0);
+    };
+    auto finish = [&](int y, uint32_t iv) {  // walk to row y's quantile and store it
+        if (!active) return;
+        const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
+        const int n = nr * nc;  // at most 257 * 257
+        int rho = (int)ceil(a.q * (double)n);
+        if (rho < 1) rho = 1;
+        walk<PACK>(hb, rho, Q, lt);
+        a.Q[(int64_t)y * a.ldQ + j] = (uint8_t)Q;
+        if (a.mask) a.mask[(int64_t)y * a.ldM + j] = (iv < (uint32_t)Q) ? 1 : 0;
+    };
+
+    if (!TWO && wmax <= 4 * PGROUP) {
+        // rows entering and leaving the window of row y (y + u and y - o)
+        // and the pixels: A holds row y+1's, B row y+2's (two rows ahead)
+        RowBytes<TWO> eA, lA, eB, lB;
+        uint32_t pxA = 0, pxB = 0;
+        auto load_rows = [&](int y, RowBytes<TWO> &e, RowBytes<TWO> &l) {
+            if (y + a.u < H) e.load(rowp(y + a.u), nb, lane);
+            if (y - a.o >= 0) l.load(rowp(y - a.o), nb, lane);
+        };
+        uint32_t px = pixel(y0);
+        if (y0 + 1 < y1) {
+            load_rows(y0 + 1, eA, lA);
+            pxA = pixel(y0 + 1);
+        }
+        if (y0 + 2 < y1) {
+            load_rows(y0 + 2, eB, lB);
+            pxB = pixel(y0 + 2);
+        }
+        PipeRow S;
+        uint32_t de[PGROUP + 1], dl[PGROUP + 1];
+        for (int y = y0; y < y1; ++y) {
+            if (y > y0) count_below(S, Q, lt);  // S: row y's updates
+            const int yn = y + 1;
+            if (yn < y1) {
+                int se, sl;
+                fetch_rows(de, dl, se, sl, eA, lA, rel);  // before this row's atomics
+                if (y > y0) apply_rows(hist, S);
+                const bool has_e = yn + a.u < H, has_l = yn - a.o >= 0;
+                if (has_e && has_l && !clip && wmax == 4 * PGROUP)
+                    decode_rows<PACK, true>(S, de, dl, se, sl, has_e, has_l, wmax, nc, lane4);
+                else
+                    decode_rows<PACK, false>(S, de, dl, se, sl, has_e, has_l, wmax, nc, lane4);
+            } else if (y > y0) {
+                apply_rows(hist, S);
+            }
+            const uint32_t iv = px;
+            // advance the load pipeline: A <- B, B <- row y + 3
+            px = pxA;
+            eA = eB;
+            lA = lB;
+            pxA = pxB;
+            if (y + 3 < y1) {
+                load_rows(y + 3, eB, lB);
+                pxB = pixel(y + 3);
+            }
+            finish(y, iv);
+        }
+        return;
+    }
+
     // rows entering and leaving the window of row y: y + u and y - o; with
     // them the lane's own pixel of row y (for the mask), one row ahead
     RowBytes<TWO> ne, nl;
@@ -318,8 +485,7 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
             if (y + a.u < H) ne.load(rowp(y + a.u), nb, lane);
             if (y - a.o >= 0) nl.load(rowp(y - a.o), nb, lane);
         }
-        const __amdgpu_buffer_rsrc_t d = qrsrc(a.I + (int64_t)y * a.ldI + x0, (uint32_t)(W - x0));
-        npx = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, lane, 0, 0);
+        npx = pixel(y);
     };
     load_row(y0);
     for (int y = y0; y < y1; ++y) {
@@ -330,22 +496,14 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
             const bool has_e = y + a.u < H, has_l = y - a.o >= 0;
             slide_rows<PACK, TWO, true>(hist, lane4, e, l, has_e, has_l, rel, nc, wmax, clip, Q, lt);
         }
-        if (!active) continue;
-        const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
-        const int64_t n = (int64_t)nr * nc;
-        int64_t rho = (int64_t)ceil(a.q * (double)n);
-        if (rho < 1) rho = 1;
-        walk<PACK>(hb, rho, Q, lt);
-        a.Q[(int64_t)y * a.ldQ + j] = (uint8_t)Q;
-        if (a.mask) a.mask[(int64_t)y * a.ldM + j] = (iv < (uint32_t)Q) ? 1 : 0;
+        finish(y, iv);
     }
 }
 
 template <bool PACK, bool TWO>
 void launch_variant(const QuantJob &a, int blocks, int seg, int nsy, hipStream_t stream)
 {
-    const size_t lds = (PACK ? 128 : 256) * QLANES * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_quantile<PACK, TWO>), dim3(blocks), dim3(QLANES), lds, stream, a, seg, nsy);
+    hipLaunchKernelGGL((k_quantile<PACK, TWO>), dim3(blocks), dim3(QLANES), 0, stream, a, seg, nsy);
 }
 
 }  // namespace
