@@ -219,17 +219,18 @@ __device__ __forceinline__ void walk(const uint32_t *hb, int rho, int &Q, int &l
         // the word of bin Q-1 and the WALK_WORDS-1 words below it
         const int w0 = (Q - 1) / BPW;
         const int lowest = (w0 - WALK_WORDS + 1 > 0 ? w0 - WALK_WORDS + 1 : 0) * BPW;
+        // WALK_WORDS consecutive words from `base` (a multiple-of-64-word
+        // stride apart, read in pairs), covering the word of Q-1 and those
+        // below it; words above Q-1's are read but not stepped to
+        const int base = lowest / BPW;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
-        for (int t = 0; t < WALK_WORDS; ++t) {
-            const int wi = w0 - t;  // clamped reads: bins below 0 are never stepped to
-            wd[t] = hb[(wi > 0 ? wi : 0) * QLANES];
-        }
+        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = hb[(base + t) * QLANES];
 #pragma unroll
-        for (int t = 0; t < WALK_WORDS; ++t) {
+        for (int t = WALK_WORDS - 1; t >= 0; --t) {
 #pragma unroll
             for (int hi = BPW - 1; hi >= 0; --hi) {
-                const int g = (w0 - t) * BPW + hi;
+                const int g = (base + t) * BPW + hi;
                 const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
                 const bool step = g == Q - 1 && g >= lowest && lt >= rho;
                 lt = step ? lt - cnt : lt;
@@ -241,18 +242,19 @@ __device__ __forceinline__ void walk(const uint32_t *hb, int rho, int &Q, int &l
     while (!found) {
         // the word of bin Q and the WALK_WORDS-1 words above it
         const int w0 = Q / BPW;
+        // WALK_WORDS consecutive words from `base`, covering Q's word and
+        // those above it (base < w0 only at the top, where bins below Q are
+        // skipped and the walk stops at bin 255)
+        const int base = w0 < NWORDS - WALK_WORDS ? w0 : NWORDS - WALK_WORDS;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
-        for (int t = 0; t < WALK_WORDS; ++t) {
-            const int wi = w0 + t;  // clamped reads: the walk stops at bin 255
-            wd[t] = hb[(wi < NWORDS - 1 ? wi : NWORDS - 1) * QLANES];
-        }
+        for (int t = 0; t < WALK_WORDS; ++t) wd[t] = hb[(base + t) * QLANES];
         const int q0 = Q;
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) {
 #pragma unroll
             for (int hi = 0; hi < BPW; ++hi) {
-                const int g = (w0 + t) * BPW + hi;
+                const int g = (base + t) * BPW + hi;
                 const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
                 const bool live = !found && g >= q0;
                 const bool hit = live && (g >= 255 || lt + cnt >= rho);
@@ -261,7 +263,7 @@ __device__ __forceinline__ void walk(const uint32_t *hb, int rho, int &Q, int &l
                 found = found || hit;
             }
         }
-        Q = found ? Q : (w0 + WALK_WORDS) * BPW;
+        Q = found ? Q : (base + WALK_WORDS) * BPW;
     }
 }
 
