@@ -25,8 +25,11 @@
 // inputs are real-valued, so float32 running sums would drift); the epilogue
 // lane takes columns t, t+64, t+128, t+192 of its wave's 256, so prefix
 // reads are conflict-free and each load or store instruction covers 64
-// consecutive elements.  Per-pixel arithmetic after the sums is float32,
-// except n S2 - S1^2, which is formed in binary64 to avoid cancellation.
+// consecutive elements.  After the sums, the forward's per-pixel arithmetic
+// is float32 except n S2 - S1^2 (binary64, against cancellation); the
+// backward evaluates m, s, t and z in binary64 (z scales every gradient term,
+// and the k and R gradients are sums with cancellation), then the sigmoid
+// and the gradient fields in float32.
 #include "../../include/binarize.h"
 #include "internal.hpp"
 
