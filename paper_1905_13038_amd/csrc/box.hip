@@ -682,6 +682,27 @@ __device__ __forceinline__ void batched_tile(const BoxJob &a, int tx, int sy, ui
     else box_tile<MODE, false, MS>(a, tx, sy, smem);
 }
 
+// A word of the batch workspace, the same for every lane.  The workspace is
+// read with vector loads (the kernel also writes it: the tile counter), so
+// without this the compiler keeps job fields in vector registers, and every
+// buffer access through a resource built from them becomes a loop over the
+// distinct values of the wavefront.
+__device__ __forceinline__ int uniform_word(const int *p) { return (int)uniform((uint32_t)*p); }
+
+// The job record at p, every field taken from the first lane.
+__device__ __forceinline__ BoxJob uniform_job(const BoxJob *p)
+{
+    static_assert(sizeof(BoxJob) % 4 == 0, "a job record is a whole number of words");
+    constexpr int N = (int)(sizeof(BoxJob) / 4);
+    const int *src = (const int *)p;
+    int w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = uniform_word(src + i);
+    BoxJob j;
+    __builtin_memcpy(&j, w, sizeof(BoxJob));
+    return j;
+}
+
 // Persistent grid over the tiles of a ragged batch.  Tiles are numbered in the
 // order of the job array (largest per-tile work first); prefix[i] is the first
 // tile of job i and prefix[count] the total.  The last workgroup to finish
@@ -691,10 +712,10 @@ template <typename TileFn>
 __device__ __forceinline__ void batched_loop(BatchHeader *hdr, TileFn tile)
 {
     __shared__ int s_tile;
-    const int count = hdr->count;
+    const int count = uniform_word(&hdr->count);
     const BoxJob *jobs = (const BoxJob *)(hdr + 1);
     const int *prefix = (const int *)(jobs + count);
-    const int total = prefix[count];
+    const int total = uniform_word(prefix + count);
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int)atomicAdd(&hdr->next_tile, 1u);
         __syncthreads();
@@ -704,11 +725,11 @@ __device__ __forceinline__ void batched_loop(BatchHeader *hdr, TileFn tile)
         int lo = 0, hi = count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (prefix[mid] <= t) lo = mid;
+            if (uniform_word(prefix + mid) <= t) lo = mid;
             else hi = mid;
         }
-        const BoxJob &a = jobs[lo];
-        const int local = t - prefix[lo];
+        const BoxJob a = uniform_job(jobs + lo);
+        const int local = t - uniform_word(prefix + lo);
         const int tx = local / a.nsy;
         tile(a, tx, local - tx * a.nsy);
         __syncthreads();  // the tile's LDS is free before the next claim
