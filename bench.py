@@ -208,7 +208,8 @@ def extras(sets, host, args):
             for img, p, (mk, mn, sd) in zip(imgs, params, outs):
                 Hh, Ww = img.shape
                 rc = lib.bz_sauvola(img.data_ptr(), Hh, Ww, Ww, p["h"], p["w"], p["k"], p["R"],
-                                    mk.data_ptr(), Ww, mn.data_ptr(), sd.data_ptr(), Ww, st)
+                                    mk.data_ptr(), mk.stride(0), mn.data_ptr(), sd.data_ptr(),
+                                    mn.stride(0), st)
                 if rc != 0:
                     raise RuntimeError("status %d" % rc)
         plain_us = _loop_us(plain, 5, warm=1)

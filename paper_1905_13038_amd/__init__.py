@@ -197,6 +197,11 @@ class BatchPlan:
     h, w, k, R (optional, default 128), method ("sauvola" or "niblack"), stats
     (optional bool, default True: also write mean/std).  strips: optional list
     of per-image strip heights (rows), e.g. from ``tune.strips_for``.
+
+    The outputs are (H, W) views of row-padded storage: every mask row and
+    every mean/std row starts on a 64-byte boundary (pitch W rounded up to 64
+    bytes and to 16 floats), so a wavefront's stores never straddle two
+    64-byte segments of a row.
     """
 
     def __init__(self, images, params, strips=None):
@@ -210,10 +215,12 @@ class BatchPlan:
             if img.device != dev:
                 raise ValueError("all images must be on one device")
             self.images.append(img)
-            mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+            ld_mask = -(-W // 64) * 64
+            ld_ms = -(-W // 16) * 16
+            mask = torch.empty((H, ld_mask), dtype=torch.uint8, device=dev)[:, :W]
             stats = p.get("stats", True)
-            mean = torch.empty((H, W), dtype=torch.float32, device=dev) if stats else None
-            std = torch.empty((H, W), dtype=torch.float32, device=dev) if stats else None
+            mean = torch.empty((H, ld_ms), dtype=torch.float32, device=dev)[:, :W] if stats else None
+            std = torch.empty((H, ld_ms), dtype=torch.float32, device=dev)[:, :W] if stats else None
             self.masks.append(mask)
             self.means.append(mean)
             self.stds.append(std)
@@ -221,7 +228,7 @@ class BatchPlan:
             items[i] = bz_item(img.data_ptr(), mask.data_ptr(),
                                mean.data_ptr() if mean is not None else None,
                                std.data_ptr() if std is not None else None,
-                               H, W, int(p["h"]), int(p["w"]), ld, W, W if stats else 0,
+                               H, W, int(p["h"]), int(p["w"]), ld, ld_mask, ld_ms if stats else 0,
                                float(p["k"]), float(p.get("R", 128.0)),
                                METHOD_SAUVOLA if method == "sauvola" else METHOD_NIBLACK)
         self._items = items

@@ -145,3 +145,23 @@ def test_autotuned_strips(bz):
     for img, p, (mk, m, s) in zip(imgs, params, plan.outputs()):
         mk0, m0, s0 = plain(bz, img, p)
         assert torch.equal(mk, mk0) and torch.equal(m, m0) and torch.equal(s, s0)
+
+
+def test_plan_outputs_rows_on_64_byte_boundaries(bz):
+    # BatchPlan pads its output rows so that each row starts on a 64-byte
+    # boundary; the values match plain calls with contiguous outputs
+    rng = np.random.default_rng(11)
+    imgs = [dev(gen_document(int(rng.integers(60, 200)), W, 90 + i, noise=10.0, stain=True))
+            for i, W in enumerate((37, 64, 101, 250))]
+    params = [{"h": 9, "w": 13, "k": 0.3, "method": "sauvola"},
+              {"h": 15, "w": 15, "k": 0.2, "method": "niblack"},
+              {"h": 5, "w": 3, "k": 0.5}, {"h": 31, "w": 21, "k": 0.4}]
+    plan = bz.BatchPlan(imgs, params)
+    plan.run()
+    torch.cuda.synchronize()
+    for img, p, (mk, m, s) in zip(imgs, params, plan.outputs()):
+        assert mk.shape == img.shape and m.shape == img.shape
+        assert mk.stride(0) % 64 == 0 and (4 * m.stride(0)) % 64 == 0 and m.stride(0) == s.stride(0)
+        assert mk.data_ptr() % 64 == 0 and m.data_ptr() % 64 == 0 and s.data_ptr() % 64 == 0
+        mk0, m0, s0 = plain(bz, img, p)
+        assert torch.equal(mk, mk0) and torch.equal(m, m0) and torch.equal(s, s0)
