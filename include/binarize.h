@@ -46,7 +46,7 @@ typedef enum {
                              image (h * ld + W bytes) spanning 2^31 bytes or more,
                              or one float32 image of the soft calls spanning
                              ((H - 1) * ld + W) 2^29 elements or more */
-    BZ_ERR_ALIAS = 3,     /* an output overlaps the input */
+    BZ_ERR_ALIAS = 3,     /* an output overlaps the input or another output */
     BZ_ERR_WORKSPACE = 4, /* caller workspace too small */
     BZ_ERR_HIP = 5        /* the HIP runtime reported an error */
 } bz_status;
@@ -135,9 +135,11 @@ size_t bz_batched_workspace_size(int count);
  * descriptors, read during the call; `workspace` is device memory of at least
  * bz_batched_workspace_size(count) bytes, 64-byte aligned, that must stay
  * untouched until the launch completes.  Each item's outputs equal those of
- * bz_sauvola / bz_niblack on that item alone.  Items must not alias each
- * other's outputs (not checked).  Synchronises `stream` once, after the
- * descriptor upload and before the launch.
+ * bz_sauvola / bz_niblack on that item alone.  No output may overlap another
+ * item's output or input (the items run concurrently): such a batch is
+ * rejected with BZ_ERR_ALIAS before any device work; inputs may overlap each
+ * other.  Synchronises `stream` once, after the descriptor upload and before
+ * the launch.
  */
 bz_status bz_sauvola_batched(const bz_item *items, int count, void *workspace,
                              size_t ws_bytes, bz_stream stream);

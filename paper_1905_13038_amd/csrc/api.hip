@@ -152,6 +152,38 @@ bz_status threshold_call(int mode, const uint8_t *I, int H, int W, ptrdiff_t ld_
     return run_box(j, (hipStream_t)stream);
 }
 
+// Cross-item aliasing of a batch: no output byte range may overlap another
+// output range or any input range (inputs may share memory).  The items run
+// concurrently, so such an overlap would make the results depend on timing.
+// Sorted sweep over the ranges: a range overlaps an earlier one exactly when
+// it starts below that range's end.
+bz_status check_batch_aliasing(const bz_item *items, int count)
+{
+    struct Tagged {
+        Range r;
+        bool out;
+    };
+    std::vector<Tagged> v;
+    v.reserve((size_t)count * 4);
+    for (int i = 0; i < count; ++i) {
+        const bz_item &it = items[i];
+        v.push_back({span(it.I, it.H, it.W, it.ld_I, 1), false});
+        v.push_back({span(it.mask, it.H, it.W, it.ld_mask, 1), true});
+        if (it.mean) {
+            v.push_back({span(it.mean, it.H, it.W, it.ld_ms, 4), true});
+            v.push_back({span(it.std, it.H, it.W, it.ld_ms, 4), true});
+        }
+    }
+    std::sort(v.begin(), v.end(), [](const Tagged &x, const Tagged &y) { return x.r.lo < y.r.lo; });
+    uintptr_t end_in = 0, end_out = 0;  // largest end so far of each kind
+    for (const Tagged &x : v) {
+        if (x.r.lo < end_out || (x.out && x.r.lo < end_in)) return BZ_ERR_ALIAS;
+        if (x.out) end_out = std::max(end_out, x.r.hi);
+        else end_in = std::max(end_in, x.r.hi);
+    }
+    return BZ_OK;
+}
+
 // Default strip height of a batched image: long enough that the h-1 priming
 // rows stay a small part of a tile.
 int default_batch_strip(int h)
@@ -304,6 +336,8 @@ bz_status bz_batched_plan(const bz_item *items, int count, const int *strip_rows
         // the lanes' columns (priming rows cost about a twelfth of a row)
         work[(size_t)i] = (int64_t)(12 * j.strip + j.h) * (int64_t)std::min(j.W, COLS_PER_LANE * BATCH_THREADS);
     }
+    const bz_status alias = check_batch_aliasing(items, count);
+    if (alias != BZ_OK) return alias;
     std::vector<int> order((size_t)count);
     for (int i = 0; i < count; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(),

@@ -111,3 +111,33 @@ def test_python_binding_refuses_host_tensors(bz):
     import torch
     with pytest.raises(ValueError):
         bz.sauvola(torch.zeros((8, 8), dtype=torch.uint8), 3, 3)
+
+
+def test_batch_rejects_cross_item_aliasing():
+    # the items of a batch run concurrently: an output overlapping another
+    # item's output or input is rejected before any device work; items may
+    # share an input.  Run in a child with BZ_FAULT_INJECT=launch, so a batch
+    # that passes validation reports BZ_ERR_HIP instead of touching a device.
+    code = r'''
+import ctypes
+import paper_1905_13038_amd as b
+L = b.lib
+def item(I, mask, mean, std):
+    return b.bz_item(I, mask, mean, std, 32, 40, 7, 9, 40, 40, 40 if mean else 0, 0.3, 128.0,
+                     b.METHOD_SAUVOLA)
+WS = 0x4000000
+nb = L.bz_batched_workspace_size(2)
+def plan(a, c):
+    arr = (b.bz_item * 2)(a, c)
+    return L.bz_batched_plan(arr, 2, None, WS, nb, None)
+A = item(0x100000, 0x200000, 0x300000, 0x400000)
+print(plan(A, item(0x110000, 0x300000 + 64, None, None)))        # mask inside A's mean
+print(plan(A, item(0x110000, 0x210000, 0x400000 + 4 * 40, 0x500000)))  # mean inside A's std
+print(plan(A, item(0x110000, 0x100000 + 8, None, None)))         # mask inside A's input
+print(plan(A, item(0x100000, 0x210000, 0x310000, 0x410000)))     # shares A's input: valid
+print(plan(A, item(0x110000, 0x210000, None, None)))             # disjoint: valid
+'''
+    env = dict(os.environ, BZ_FAULT_INJECT="launch")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
+                         text=True, check=True)
+    assert out.stdout.split() == ["3", "3", "3", "5", "5"]
