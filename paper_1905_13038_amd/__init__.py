@@ -138,15 +138,44 @@ def window_mean_std(img: torch.Tensor, h: int, w: int):
     return m, s
 
 
+def _given_output(t, name, H, W, dtype, device):
+    """A caller-provided output: the kernels write H rows of W elements at
+    row stride t.stride(0), so shape, dtype, device and unit column stride
+    must match exactly."""
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device:
+        raise ValueError("%s must be a %s tensor on %s" % (name, dtype, device))
+    if tuple(t.shape) != (H, W) or (W > 1 and t.stride(1) != 1) or (H > 1 and t.stride(0) < W):
+        raise ValueError("%s must have shape (%d, %d) with unit column stride" % (name, H, W))
+    return t
+
+
 def _outputs(img, H, W, stats, mask, mean, std):
     if mask is None:
         mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
-    if stats:
-        if mean is None:
-            mean = torch.empty((H, W), dtype=torch.float32, device=img.device)
-        if std is None:
-            std = torch.empty((H, W), dtype=torch.float32, device=img.device)
+    else:
+        _given_output(mask, "mask", H, W, torch.uint8, img.device)
+    if not stats:
+        if mean is not None or std is not None:
+            raise ValueError("mean/std outputs given with stats=False")
+        return mask, None, None
+    for t, name in ((mean, "mean"), (std, "std")):
+        if t is not None:
+            _given_output(t, name, H, W, torch.float32, img.device)
+    # mean and std share one row stride (the C ABI takes one ld for both)
+    ref = mean if mean is not None else std
+    ld_ms = _ld(ref, W) if ref is not None else W
+    if mean is None:
+        mean = torch.empty_strided((H, W), (ld_ms, 1), dtype=torch.float32, device=img.device)
+    if std is None:
+        std = torch.empty_strided((H, W), (ld_ms, 1), dtype=torch.float32, device=img.device)
+    if _ld(mean, W) != _ld(std, W):
+        raise ValueError("mean and std must share one row stride")
     return mask, mean, std
+
+
+def _ld(t, W):
+    """Row stride of an output for the C ABI (W for a single row)."""
+    return t.stride(0) if t.shape[0] > 1 else W
 
 
 def sauvola(img: torch.Tensor, h: int, w: int, k: float = 0.5, R: float = 128.0,
@@ -155,9 +184,9 @@ def sauvola(img: torch.Tensor, h: int, w: int, k: float = 0.5, R: float = 128.0,
     float32 window mean and standard deviation.  Returns (mask, mean, std)."""
     img, H, W, ld = _image(img)
     mask, mean, std = _outputs(img, H, W, stats, mask, mean, std)
-    ld_ms = mean.stride(0) if mean is not None else 0
+    ld_ms = _ld(mean, W) if mean is not None else 0
     _check(lib.bz_sauvola(img.data_ptr(), H, W, ld, h, w, float(k), float(R), mask.data_ptr(),
-                          mask.stride(0), mean.data_ptr() if mean is not None else None,
+                          _ld(mask, W), mean.data_ptr() if mean is not None else None,
                           std.data_ptr() if std is not None else None, ld_ms, _stream(img)),
            "bz_sauvola")
     return mask, mean, std
@@ -168,9 +197,9 @@ def niblack(img: torch.Tensor, h: int, w: int, k: float = -0.2, stats: bool = Tr
     """Niblack mask (1 where I < m + k s); returns (mask, mean, std)."""
     img, H, W, ld = _image(img)
     mask, mean, std = _outputs(img, H, W, stats, mask, mean, std)
-    ld_ms = mean.stride(0) if mean is not None else 0
+    ld_ms = _ld(mean, W) if mean is not None else 0
     _check(lib.bz_niblack(img.data_ptr(), H, W, ld, h, w, float(k), mask.data_ptr(),
-                          mask.stride(0), mean.data_ptr() if mean is not None else None,
+                          _ld(mask, W), mean.data_ptr() if mean is not None else None,
                           std.data_ptr() if std is not None else None, ld_ms, _stream(img)),
            "bz_niblack")
     return mask, mean, std

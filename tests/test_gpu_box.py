@@ -238,6 +238,29 @@ def test_mask_only_and_strided_outputs(bz):
     check_moments(bm[:, 1:641], bs[:, 1:641], ref, ref["S1"], ref["S2"], oracle.count_map(300, 640, 21, 21))
 
 
+def test_given_outputs_are_checked(bz):
+    # outputs the caller passes must match the image: shape, dtype, device and
+    # unit column stride, and mean/std one row stride; a given mean with a
+    # padded stride gets a std of the same stride
+    d = dev(gen_document(40, 50, 6, noise=10.0))
+    u8 = lambda *s: torch.zeros(s, dtype=torch.uint8, device="cuda")
+    f32 = lambda *s: torch.zeros(s, dtype=torch.float32, device="cuda")
+    bad = [dict(mask=u8(40, 49)), dict(mask=u8(50, 40).t()),
+           dict(mask=torch.zeros((40, 50), dtype=torch.int32, device="cuda")),
+           dict(mask=torch.zeros((40, 50), dtype=torch.uint8)),
+           dict(mean=f32(40, 50).double()), dict(mean=f32(50, 40).t()),
+           dict(mean=f32(40, 50), std=f32(40, 60)[:, :50])]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            bz.sauvola(d, 7, 7, **kw)
+    with pytest.raises(ValueError):
+        bz.sauvola(d, 7, 7, stats=False, mean=f32(40, 50))
+    m0, s0 = bz.sauvola(d, 7, 7)[1:]
+    wide = f32(40, 64)
+    _, m, s = bz.sauvola(d, 7, 7, mean=wide[:, :50])
+    assert s.stride(0) == 64 and torch.equal(m, m0) and torch.equal(s, s0)
+
+
 @pytest.mark.parametrize("strip,threads", [(1, 0), (3, 0), (50, 128), (7, 64), (0, 192)])
 def test_tiling_overrides(bz, monkeypatch, strip, threads):
     # other strip heights and block sizes give identical results
