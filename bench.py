@@ -119,12 +119,66 @@ def _loop_us(fn, n, warm=3):
     return a.elapsed_time(b) * 1e3 / n
 
 
+def ragged_batch_inputs(dev):
+    """The 256-page ragged batch: crops (at seeded offsets) of one generated
+    4096 x 4096 page, each copied into its own tensor, with the shapes and
+    parameters of the batch recipe.  Returns (images, params)."""
+    import torch
+    from docgen import batch_specs, gen_document
+    specs = batch_specs()
+    big = torch.from_numpy(gen_document(4096, 4096, 4, noise=10.0, stain=True)).to(dev)
+    rng = np.random.default_rng(4)
+    imgs, params = [], []
+    for d in specs:
+        y = int(rng.integers(0, 4096 - d["H"] + 1))
+        x = int(rng.integers(0, 4096 - d["W"] + 1))
+        imgs.append(big[y:y + d["H"], x:x + d["W"]].clone())
+        params.append({"h": d["h"], "w": d["w"], "k": d["k"], "R": d["R"], "method": "sauvola"})
+    return imgs, params
+
+
+def soft_workload(dev, B=32, Hs=1024, Ws=1024, win=32, tau=2.0):
+    """The differentiable workload (B float32 pages, h = w = win): returns
+    (fwd, bwd, workspace bytes), each call one launch sequence on the current
+    stream."""
+    import torch
+    import paper_1905_13038_amd as bz
+    from docgen import soft_batch
+    lib = bz.lib
+    st = torch.cuda.current_stream().cuda_stream
+    I, kk, Wr = soft_batch(B, Hs, Ws)
+    I = torch.from_numpy(np.ascontiguousarray(I)).to(dev)
+    kd = torch.from_numpy(np.asarray(kk, dtype=np.float32)).to(dev)
+    Rd = torch.tensor([128.0], dtype=torch.float32, device=dev)
+    gy = torch.from_numpy(np.ascontiguousarray(Wr, dtype=np.float32)).to(dev)
+    y = torch.empty_like(I)
+    gI = torch.empty_like(I)
+    gk = torch.empty_like(kd)
+    gR = torch.empty_like(Rd)
+    nb = int(lib.bz_soft_workspace_size(B, Hs, Ws))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def fwd(i=0):
+        rc = lib.bz_soft_sauvola_fwd(I.data_ptr(), B, Hs, Ws, Ws, win, win, kd.data_ptr(),
+                                     Rd.data_ptr(), tau, y.data_ptr(), st)
+        if rc != 0:
+            raise RuntimeError("status %d" % rc)
+
+    def bwd(i=0):
+        rc = lib.bz_soft_sauvola_bwd(I.data_ptr(), gy.data_ptr(), B, Hs, Ws, Ws, win, win,
+                                     kd.data_ptr(), Rd.data_ptr(), tau, gI.data_ptr(),
+                                     gk.data_ptr(), gR.data_ptr(), ws.data_ptr(), nb, st)
+        if rc != 0:
+            raise RuntimeError("status %d" % rc)
+    return fwd, bwd, nb
+
+
 def extras(sets, host, args):
     """The other measured workloads: window sweep, Niblack, mask-only,
     mean/std, cache-warm, ragged batch, soft fwd+bwd, quantiles."""
     import torch
     import paper_1905_13038_amd as bz
-    from docgen import batch_specs, gen_document, soft_batch
+    from docgen import gen_document
 
     lib = bz.lib
     H, W = host.shape
@@ -189,17 +243,7 @@ def extras(sets, host, args):
     def batch():
         # 256 ragged pages: crops (at seeded offsets) of one generated 4096 x 4096
         # page, each copied into its own tensor
-        specs = batch_specs()
-        dev = sets[0][0].device
-        big = torch.from_numpy(gen_document(4096, 4096, 4, noise=10.0, stain=True)).to(dev)
-        rng = np.random.default_rng(4)
-        imgs, params = [], []
-        for d in specs:
-            y = int(rng.integers(0, 4096 - d["H"] + 1))
-            x = int(rng.integers(0, 4096 - d["W"] + 1))
-            imgs.append(big[y:y + d["H"], x:x + d["W"]].clone())
-            params.append({"h": d["h"], "w": d["w"], "k": d["k"], "R": d["R"], "method": "sauvola"})
-        del big
+        imgs, params = ragged_batch_inputs(sets[0][0].device)
         tot = sum(int(t.numel()) for t in imgs)
         plan = bz.BatchPlan(imgs, params)
         outs = plan.outputs()
@@ -227,31 +271,7 @@ def extras(sets, host, args):
 
     def soft():
         B, Hs, Ws, win, tau = 32, 1024, 1024, 32, 2.0
-        I, kk, Wr = soft_batch(B, Hs, Ws)
-        dev = sets[0][0].device
-        I = torch.from_numpy(np.ascontiguousarray(I)).to(dev)
-        kd = torch.from_numpy(np.asarray(kk, dtype=np.float32)).to(dev)
-        Rd = torch.tensor([128.0], dtype=torch.float32, device=dev)
-        gy = torch.from_numpy(np.ascontiguousarray(Wr, dtype=np.float32)).to(dev)
-        y = torch.empty_like(I)
-        gI = torch.empty_like(I)
-        gk = torch.empty_like(kd)
-        gR = torch.empty_like(Rd)
-        nb = int(lib.bz_soft_workspace_size(B, Hs, Ws))
-        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-
-        def fwd(i):
-            rc = lib.bz_soft_sauvola_fwd(I.data_ptr(), B, Hs, Ws, Ws, win, win, kd.data_ptr(),
-                                         Rd.data_ptr(), tau, y.data_ptr(), st)
-            if rc != 0:
-                raise RuntimeError("status %d" % rc)
-
-        def bwd(i):
-            rc = lib.bz_soft_sauvola_bwd(I.data_ptr(), gy.data_ptr(), B, Hs, Ws, Ws, win, win,
-                                         kd.data_ptr(), Rd.data_ptr(), tau, gI.data_ptr(),
-                                         gk.data_ptr(), gR.data_ptr(), ws.data_ptr(), nb, st)
-            if rc != 0:
-                raise RuntimeError("status %d" % rc)
+        fwd, bwd, nb = soft_workload(sets[0][0].device, B, Hs, Ws, win, tau)
         f_us = _loop_us(fwd, 10)
         b_us = _loop_us(bwd, 10)
         n = B * Hs * Ws
@@ -305,6 +325,9 @@ def main():
                     help="skip the other workloads (window sweep, batch, soft, quantiles)")
     ap.add_argument("--pmc", action="store_true",
                     help="counter run: 3 launches + 3 plain 1 GiB copies, no JSON")
+    ap.add_argument("--pmc-workload", choices=("page", "batch", "soft"), default="page",
+                    help="what --pmc launches: the headline page, the 256-page ragged batch "
+                         "(one persistent launch each), or the soft forward + backward")
     ap.add_argument("--win", type=int, default=75)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -334,8 +357,19 @@ def main():
         bz.sauvola(img, win, win, k=k, R=R, mask=mask, mean=m, std=sd)
 
     if args.pmc:
-        for i in range(3):
-            step(i)
+        if args.pmc_workload == "batch":
+            imgs, params = ragged_batch_inputs(dev)
+            plan = bz.BatchPlan(imgs, params)
+            for i in range(3):
+                plan.run()
+        elif args.pmc_workload == "soft":
+            fwd, bwd, _ = soft_workload(dev)
+            for i in range(3):
+                fwd()
+                bwd()
+        else:
+            for i in range(3):
+                step(i)
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
