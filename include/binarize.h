@@ -17,10 +17,12 @@
  *   that range the column sums fit 16 bits and the window sum of squares fits
  *   32 bits (Section 3.3).
  * Memory.  Every pointer is DEVICE memory owned by the caller unless stated
- *   otherwise.  The library never allocates, frees or synchronises; a call
- *   enqueues its kernels on `stream` and returns.  Outputs must not overlap
- *   the input (Section 3.2's aliasing assumption); overlapping byte ranges are
- *   rejected with BZ_ERR_ALIAS.  32-bit outputs must be 4-byte aligned.
+ *   otherwise.  The library never allocates or frees device memory.  A call
+ *   enqueues its kernels on `stream` and returns without synchronising; the
+ *   one exception is the set-up call bz_batched_plan, which synchronises its
+ *   stream once.  Outputs must not overlap the input or each other (Section
+ *   3.2's aliasing assumption); overlapping byte ranges are rejected with
+ *   BZ_ERR_ALIAS.  32-bit outputs must be 4-byte aligned.
  * Stream.  `stream` is a hipStream_t (NULL = the null stream).
  * Errors.  Arguments are validated before any HIP call; an invalid call
  *   returns its status and enqueues nothing.  BZ_ERR_HIP reports a launch
@@ -71,9 +73,10 @@ bz_status bz_window_sums(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, 
 /*
  * Window mean m = S1/n and population standard deviation
  * s = sqrt(n S2 - S1^2) / n (Introduction, with Algorithm 1's divisor n).
- * n S2 - S1^2 is formed exactly in 64-bit integer arithmetic; m and s are
- * float32, within 1e-6 relative of the binary64 values, and s == 0 exactly
- * where the window is constant.  mean, std: float H x W, row stride ld_out.
+ * n S2 - S1^2 is formed exactly (its terms are integers below 2^53, combined
+ * by one binary64 fused multiply-add); m and s are float32, within 1e-6
+ * relative of the binary64 values, and s == 0 exactly where the window is
+ * constant.  mean, std: float H x W, row stride ld_out.
  */
 bz_status bz_window_mean_std(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
                              float *mean, float *std, ptrdiff_t ld_out, bz_stream stream);
