@@ -29,6 +29,10 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MEANSTD, SAUVOLA, NIBLACK = 0, 1, 2
+# the remaining methods of Table 1
+WOLF, FENG, RAIS, NICK, PHANSALKAR = 3, 4, 5, 6, 7
+TABLE1_PARAMS = {WOLF: ("k", "R"), FENG: ("a1", "k1", "k2", "gamma", "R"), RAIS: (),
+                 NICK: ("k",), PHANSALKAR: ("p", "q", "k", "R")}
 
 _lib = None
 
@@ -66,6 +70,12 @@ def _load():
     lib.orc_sums_integral.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.orc_threshold.restype = None
     lib.orc_threshold.argtypes = [P, i32, i32, i64, i32, i32, P, P, i32, f32, f32, P, P, P, P]
+    lib.orc_global_stats.restype = None
+    lib.orc_global_stats.argtypes = [P, i32, i32, i64, P, P]
+    lib.orc_table1_t.restype = f64
+    lib.orc_table1_t.argtypes = [i32, f64, f64, f64, P, f64, f64, f64]
+    lib.orc_table1.restype = None
+    lib.orc_table1.argtypes = [P, i32, i32, i64, i32, i32, P, P, i32, P, P, P, P]
     lib.orc_sauvola_sqrtfree.restype = None
     lib.orc_sauvola_sqrtfree.argtypes = [P, i32, i32, i64, i32, i32, P, P, f32, f32, P]
     lib.orc_rank.restype = i64
@@ -196,6 +206,57 @@ def sauvola(I, h, w, k=0.5, R=128.0, **kw):
 def niblack(I, h, w, k=-0.2, **kw):
     """Niblack (Table 1) in the canonical binary64 sequence."""
     return threshold(I, h, w, NIBLACK, k, 128.0, **kw)
+
+
+def global_stats(I):
+    """Table 1's global statistics of the whole image: dict(L, max, M, S, N,
+    T1, T2) with L the minimum gray level, M the mean and S the population
+    standard deviation (exact integer sums, then one binary64 sequence)."""
+    I, H, W, ld = _img(I)
+    out = np.empty(4, np.float64)
+    sums = np.empty(3, np.uint64)
+    _load().orc_global_stats(_ptr(I), H, W, ld, _ptr(out), _ptr(sums))
+    return dict(L=out[0], max=out[1], M=out[2], S=out[3], N=int(sums[0]), T1=int(sums[1]),
+                T2=int(sums[2]))
+
+
+def table1_params(method: int, params):
+    """The method's parameter vector (binary64) from a dict or a sequence."""
+    names = TABLE1_PARAMS[method]
+    if isinstance(params, dict):
+        vals = [float(params[n]) for n in names]
+    else:
+        vals = [float(v) for v in params]
+        if len(vals) != len(names):
+            raise ValueError("method %d takes %d parameters" % (method, len(names)))
+    return np.array(vals + [0.0] * (5 - len(vals)), np.float64)
+
+
+def table1_t(method: int, m: float, s: float, n: float, params, L=0.0, M=0.0, S=0.0) -> float:
+    """One threshold of Table 1 from m, s, the count n and the global L, M, S."""
+    p = table1_params(method, params)
+    return float(_load().orc_table1_t(method, m, s, n, _ptr(p), L, M, S))
+
+
+def table1(I, h: int, w: int, method: int, params, gstats=None, S1=None, S2=None):
+    """Wolf, Feng, Rais, Khurshid (NICK) or Phansalkar (Table 1): the canonical
+    binary64 moments, the method's threshold and mask = 1 iff I < t.
+    Returns dict(t, mask, m, s, gstats)."""
+    I, H, W, ld = _img(I)
+    if S1 is None:
+        S1, S2 = sums_recursive(I, h, w) if max(h, w) <= 257 else sums_integral(I, h, w)
+    S1 = np.ascontiguousarray(S1, dtype=np.uint64)
+    S2 = np.ascontiguousarray(S2, dtype=np.uint64)
+    if gstats is None:
+        gstats = global_stats(I)
+    g = np.array([gstats["L"], gstats["max"], gstats["M"], gstats["S"]], np.float64)
+    p = table1_params(method, params)
+    t = np.empty((H, W), np.float64)
+    mask = np.empty((H, W), np.uint8)
+    _load().orc_table1(_ptr(I), H, W, ld, h, w, _ptr(S1), _ptr(S2), method, _ptr(p), _ptr(g),
+                       _ptr(t), _ptr(mask))
+    base = threshold(I, h, w, MEANSTD, S1=S1, S2=S2)
+    return dict(t=t, mask=mask, m=base["m"], s=base["s"], gstats=gstats, S1=S1, S2=S2)
 
 
 def sauvola_sqrtfree(I, h: int, w: int, k: float, R: float, S1=None, S2=None):

@@ -241,6 +241,133 @@ void orc_threshold(const uint8_t *I, int H, int W, int64_t ld, int h, int w,
     }
 }
 
+/* Global statistics of an image, in Table 1's notation: L = minimum gray
+ * level, M = mean and S = population standard deviation of all N = H W gray
+ * levels.  The sums T1 = sum I and T2 = sum I^2 are exact integers and
+ * N T2 - T1^2 is exact in 128 bits; then, each operation rounded once,
+ * M = T1 / N and S = sqrt(VN / (N N)) with VN = N T2 - T1^2 rounded to
+ * binary64.  out: L, the maximum, M, S; sums: N, T1, T2. */
+void orc_global_stats(const uint8_t *I, int H, int W, int64_t ld, double out[4], uint64_t sums[3])
+{
+    uint64_t T1 = 0, T2 = 0;
+    unsigned lo = 255, hi = 0;
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const unsigned g = I[(int64_t)i * ld + j];
+            T1 += g;
+            T2 += (uint64_t)g * g;
+            if (g < lo) lo = g;
+            if (g > hi) hi = g;
+        }
+    }
+    const uint64_t N = (uint64_t)H * (uint64_t)W;
+    const unsigned __int128 VN = (unsigned __int128)N * T2 - (unsigned __int128)T1 * T1;
+    const double Nd = (double)N;
+    out[0] = (double)lo;
+    out[1] = (double)hi;
+    out[2] = (double)T1 / Nd;
+    out[3] = sqrt((double)VN / (Nd * Nd));
+    sums[0] = N;
+    sums[1] = T1;
+    sums[2] = T2;
+}
+
+/* The remaining thresholds of Table 1, each in one binary64 sequence (every
+ * operation rounded once, nothing fused) from the canonical m, s of
+ * orc_threshold and the global L, M, S of orc_global_stats:
+ *   Wolf:       t = m - k (m - L) (1 - s/R)             p = {k, R}
+ *   Feng:       t = a1 m + k1 (s/R)^(1+g) (m - L)
+ *                    + k2 (s/R)^g L                       p = {a1, k1, k2, g, R}
+ *   Rais:       t = m + 0.3 (m s - M S) / max{m s, M S} s (the fraction is
+ *               taken as 0 where both products are 0)      p = {}
+ *   Khurshid (NICK): t = m + k sqrt(s^2 + m^2 (n-1)/n), with the window's
+ *               in-bounds count n in place of h w          p = {k}
+ *   Phansalkar: t = m (1 + p e^(-q m) + k (s/R - 1))      p = {p, q, k, R}
+ * mask = 1 iff I < t.  pow and exp are the C library's. */
+enum { ORC_WOLF = 3, ORC_FENG = 4, ORC_RAIS = 5, ORC_NICK = 6, ORC_PHANSALKAR = 7 };
+
+double orc_table1_t(int method, double m, double s, double n, const double *p, double L, double M,
+                    double S)
+{
+    switch (method) {
+    case ORC_WOLF: {
+        double a = s / p[1];
+        a = 1.0 - a;
+        double b = m - L;
+        b = p[0] * b;
+        b = b * a;
+        return m - b;
+    }
+    case ORC_FENG: {
+        const double x = s / p[4];
+        const double x1 = pow(x, 1.0 + p[3]);
+        const double x0 = pow(x, p[3]);
+        const double a = p[0] * m;
+        double b = p[1] * x1;
+        b = b * (m - L);
+        double c = p[2] * x0;
+        c = c * L;
+        double t = a + b;
+        return t + c;
+    }
+    case ORC_RAIS: {
+        const double a = m * s, b = M * S;
+        const double e = a > b ? a : b;
+        double f = 0.0;
+        if (e > 0.0) f = (a - b) / e;
+        double g = 0.3 * f;
+        g = g * s;
+        return m + g;
+    }
+    case ORC_NICK: {
+        const double a = s * s;
+        double b = m * m;
+        const double c = (n - 1.0) / n;
+        b = b * c;
+        const double r = sqrt(a + b);
+        const double q = p[0] * r;
+        return m + q;
+    }
+    case ORC_PHANSALKAR: {
+        double e = p[1] * m;
+        e = exp(-e);
+        const double a = p[0] * e;
+        double b = s / p[3];
+        b = b - 1.0;
+        b = p[2] * b;
+        double c = 1.0 + a;
+        c = c + b;
+        return m * c;
+    }
+    default:
+        return 0.0;
+    }
+}
+
+/* Table 1 thresholds over an image: m, s as in orc_threshold (canonical
+ * binary64), then orc_table1_t.  gstats: L, max, M, S from orc_global_stats.
+ * t and mask may be NULL; S1, S2 dense H x W. */
+void orc_table1(const uint8_t *I, int H, int W, int64_t ld, int h, int w, const uint64_t *S1,
+                const uint64_t *S2, int method, const double *p, const double *gstats, double *t_out,
+                uint8_t *mask)
+{
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const int64_t q = (int64_t)i * W + j;
+            const int64_t n = orc_count(H, W, h, w, i, j);
+            const int64_t s1 = (int64_t)S1[q], s2 = (int64_t)S2[q];
+            const int64_t Vn = n * s2 - s1 * s1;
+            const double nd = (double)n;
+            const double m = (double)s1 / nd;
+            const double v = (double)Vn / (nd * nd);
+            const double s = sqrt(v);
+            const double t = orc_table1_t(method, m, s, nd, p, gstats[0], gstats[2], gstats[3]);
+            if (t_out) t_out[q] = t;
+            if (mask) mask[q] = ((double)I[(int64_t)i * ld + j] < t) ? 1 : 0;
+        }
+    }
+}
+
 /* The square-root-free Sauvola decision of Section 3.2 (k >= 0), in binary64:
  * background (paper's output 0) iff I + m(k-1) <= 0 or
  * (I + m(k-1))^2 <= k^2 m^2 v / R^2.  Writes the paper's output bit I'. */
