@@ -116,6 +116,63 @@ bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
 /* Thresholding rule of a batched item. */
 enum { BZ_METHOD_SAUVOLA = 1, BZ_METHOD_NIBLACK = 2 };
 
+/* The other rules of Table 1, for bz_threshold. */
+enum {
+    BZ_METHOD_WOLF = 3,
+    BZ_METHOD_FENG = 4,
+    BZ_METHOD_RAIS = 5,
+    BZ_METHOD_NICK = 6, /* Khurshid et al. */
+    BZ_METHOD_PHANSALKAR = 7
+};
+
+/*
+ * Global statistics of one image (Table 1's notation: L the minimum gray
+ * level, M the mean, S the population standard deviation), as written by
+ * bz_global_stats into DEVICE memory (8-byte aligned, 48 bytes): n = H W,
+ * sum and sumsq the exact sums of I and I^2, min and max, then
+ * mean = sum / n and std = sqrt((n sumsq - sum^2) / (n n)) in binary64, with
+ * n sumsq - sum^2 formed exactly and rounded once.
+ */
+typedef struct {
+    uint64_t n, sum, sumsq;
+    uint32_t min, max;
+    double mean, std;
+} bz_global;
+
+/*
+ * Compute the global statistics of I into `stats` (device).  Three small
+ * kernels on `stream` (reset, accumulate, finish); no memset, so the call can
+ * be captured in a graph.  Deterministic (integer atomics).
+ */
+bz_status bz_global_stats(const uint8_t *I, int H, int W, ptrdiff_t ld_I, bz_global *stats,
+                          bz_stream stream);
+
+/*
+ * The other thresholding rules of Table 1, each deciding mask = 1 where
+ * I < t in one binary64 sequence from the canonical m, s (as in bz_sauvola),
+ * every operation rounded once:
+ *   BZ_METHOD_WOLF        t = m - k (m - L)(1 - s/R)          params {k, R}
+ *   BZ_METHOD_FENG        t = a1 m + k1 (s/R)^(1+g) (m - L)
+ *                             + k2 (s/R)^g L                  params {a1, k1, k2, g, R}
+ *   BZ_METHOD_RAIS        t = m + 0.3 (m s - M S) / max{m s, M S} s, the
+ *                         fraction taken as 0 where both products are 0
+ *                                                             params {} (NULL allowed)
+ *   BZ_METHOD_NICK        t = m + k sqrt(s^2 + m^2 (n-1)/n), with the
+ *                         window's in-bounds count n for h w  params {k}
+ *   BZ_METHOD_PHANSALKAR  t = m (1 + p e^(-q m) + k (s/R - 1)) params {p, q, k, R}
+ * `params` is a HOST array read during the call; every value must be finite
+ * and R > 0.  `stats` is the DEVICE record of bz_global_stats for this image
+ * (Wolf and Feng read L, Rais reads M and S; NULL allowed for NICK and
+ * Phansalkar); it must be complete when the kernel runs (same stream, or
+ * synchronised).  mask, mean, std as in bz_sauvola.  Feng's powers and
+ * Phansalkar's exponential use the device's binary64 pow and exp, so near
+ * exact ties a pixel's decision can differ from a C library's.
+ */
+bz_status bz_threshold(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int method,
+                       const double *params, const bz_global *stats, uint8_t *mask,
+                       ptrdiff_t ld_mask, float *mean, float *std, ptrdiff_t ld_ms,
+                       bz_stream stream);
+
 /* One image of a ragged batch; pointers are device memory, mean/std may be
  * NULL.  Each item has its own size, strides, window and parameters. */
 typedef struct {

@@ -15,12 +15,13 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
     "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola",
-    "LIB_PATH",
+    "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbinarize.so")
@@ -52,6 +53,10 @@ lib.bz_niblack.restype = _I
 lib.bz_niblack.argtypes = [_P, _I, _I, _PD, _I, _I, _F, _P, _PD, _P, _P, _PD, _P]
 lib.bz_window_quantile.restype = _I
 lib.bz_window_quantile.argtypes = [_P, _I, _I, _PD, _I, _I, _D, _P, _PD, _P, _PD, _P]
+lib.bz_global_stats.restype = _I
+lib.bz_global_stats.argtypes = [_P, _I, _I, _PD, _P, _P]
+lib.bz_threshold.restype = _I
+lib.bz_threshold.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _P, _P, _PD, _P, _P, _PD, _P]
 
 
 class bz_item(ctypes.Structure):
@@ -303,6 +308,70 @@ def sauvola_batched(images, params, strips=None):
     plan = BatchPlan(images, params, strips)
     plan.run()
     return plan.outputs()
+
+
+# The other rules of Table 1: C-ABI code and parameter names, in order.
+TABLE1 = {
+    "wolf": (3, ("k", "R")),
+    "feng": (4, ("a1", "k1", "k2", "gamma", "R")),
+    "rais": (5, ()),
+    "nick": (6, ("k",)),
+    "phansalkar": (7, ("p", "q", "k", "R")),
+}
+_NEEDS_GLOBAL = {"wolf", "feng", "rais"}
+GLOBAL_DTYPE = np.dtype([("n", "<u8"), ("sum", "<u8"), ("sumsq", "<u8"), ("min", "<u4"),
+                         ("max", "<u4"), ("mean", "<f8"), ("std", "<f8")])
+
+
+def global_stats(img: torch.Tensor) -> torch.Tensor:
+    """Table 1's global statistics (minimum L, mean M, standard deviation S,
+    with the exact sums) of a uint8 device image, as the 48-byte device record
+    bz_global; read it on the host with ``read_global_stats``."""
+    img, H, W, ld = _image(img)
+    rec = torch.empty(GLOBAL_DTYPE.itemsize, dtype=torch.uint8, device=img.device)
+    _check(lib.bz_global_stats(img.data_ptr(), H, W, ld, rec.data_ptr(), _stream(img)),
+           "bz_global_stats")
+    return rec
+
+
+def read_global_stats(rec: torch.Tensor) -> dict:
+    """The fields of a bz_global record (copies it to the host)."""
+    a = rec.cpu().numpy().view(GLOBAL_DTYPE)[0]
+    return {k: a[k].item() for k in GLOBAL_DTYPE.names}
+
+
+def table1_threshold(img: torch.Tensor, h: int, w: int, method: str, params=None, stats=None,
+                     with_stats: bool = True, mask=None, mean=None, std=None):
+    """Wolf, Feng, Rais, Khurshid (NICK) or Phansalkar thresholding (Table 1):
+    mask = 1 where I < t, decided in binary64.  ``params``: dict or sequence
+    in the order of ``TABLE1[method][1]`` (Rais takes none).  ``stats``: the
+    image's global-statistics record; computed here when the rule needs it and
+    none is given.  Returns (mask, mean, std)."""
+    if method not in TABLE1:
+        raise ValueError("method must be one of %s" % ", ".join(TABLE1))
+    code, names = TABLE1[method]
+    if isinstance(params, dict):
+        vals = [float(params[n]) for n in names]
+    else:
+        vals = [float(v) for v in (params or ())]
+    if len(vals) != len(names):
+        raise ValueError("%s takes parameters %s" % (method, names))
+    img, H, W, ld = _image(img)
+    if method in _NEEDS_GLOBAL and stats is None:
+        stats = global_stats(img)
+    if stats is not None and (not isinstance(stats, torch.Tensor) or stats.device != img.device
+                              or stats.dtype != torch.uint8 or stats.numel() != GLOBAL_DTYPE.itemsize
+                              or not stats.is_contiguous()):
+        raise ValueError("stats must be a 48-byte uint8 record on the image's device")
+    mask, mean, std = _outputs(img, H, W, with_stats, mask, mean, std)
+    ld_ms = _ld(mean, W) if mean is not None else 0
+    pv = (ctypes.c_double * 5)(*(vals + [0.0] * (5 - len(vals))))
+    _check(lib.bz_threshold(img.data_ptr(), H, W, ld, h, w, code, pv,
+                            stats.data_ptr() if stats is not None else None, mask.data_ptr(),
+                            _ld(mask, W), mean.data_ptr() if mean is not None else None,
+                            std.data_ptr() if std is not None else None, ld_ms, _stream(img)),
+           "bz_threshold")
+    return mask, mean, std
 
 
 def _soft_inputs(I, k, R):

@@ -268,6 +268,62 @@ bz_status bz_niblack(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int 
                           ld_ms, stream);
 }
 
+static_assert(sizeof(bz_global) == sizeof(GlobalStats), "bz_global layout");
+static_assert(BZ_METHOD_WOLF == T1_WOLF && BZ_METHOD_FENG == T1_FENG && BZ_METHOD_RAIS == T1_RAIS &&
+                  BZ_METHOD_NICK == T1_NICK && BZ_METHOD_PHANSALKAR == T1_PHANSALKAR,
+              "Table 1 rule codes");
+
+bz_status bz_global_stats(const uint8_t *I, int H, int W, ptrdiff_t ld_I, bz_global *stats,
+                          bz_stream stream)
+{
+    const bz_status st = check_image(I, H, W, ld_I, 1, 1);
+    if (st != BZ_OK) return st;
+    if (stats == nullptr || !aligned(stats, 8)) return BZ_ERR_INVALID;
+    const Range g{(uintptr_t)stats, (uintptr_t)stats + sizeof(bz_global)};
+    if (overlaps(span(I, H, W, ld_I, 1), g)) return BZ_ERR_ALIAS;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    return hip_status(launch_global_stats(I, H, W, ld_I, (GlobalStats *)stats, (hipStream_t)stream));
+}
+
+bz_status bz_threshold(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int method,
+                       const double *params, const bz_global *stats, uint8_t *mask,
+                       ptrdiff_t ld_mask, float *mean, float *stdv, ptrdiff_t ld_ms,
+                       bz_stream stream)
+{
+    int np = 0, r_at = -1;     // parameters taken; index of R (must be > 0)
+    bool needs_stats = false;  // the rule reads L, M or S
+    switch (method) {
+    case BZ_METHOD_WOLF: np = 2; r_at = 1; needs_stats = true; break;
+    case BZ_METHOD_FENG: np = 5; r_at = 4; needs_stats = true; break;
+    case BZ_METHOD_RAIS: needs_stats = true; break;
+    case BZ_METHOD_NICK: np = 1; break;
+    case BZ_METHOD_PHANSALKAR: np = 4; r_at = 3; break;
+    default: return BZ_ERR_INVALID;
+    }
+    double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (np > 0 && params == nullptr) return BZ_ERR_INVALID;
+    for (int i = 0; i < np; ++i) {
+        if (!isfinite(params[i])) return BZ_ERR_INVALID;
+        p[i] = params[i];
+    }
+    if (r_at >= 0 && !(p[r_at] > 0.0)) return BZ_ERR_INVALID;
+    if (needs_stats && (stats == nullptr || !aligned(stats, 8))) return BZ_ERR_INVALID;
+    BoxJob j;
+    const bz_status st = make_threshold_job(MODE_TABLE1, I, H, W, ld_I, h, w, 0.0f, 1.0f, mask,
+                                            ld_mask, mean, stdv, ld_ms, j);
+    if (st != BZ_OK) return st;
+    if (needs_stats) {
+        const Range g{(uintptr_t)stats, (uintptr_t)stats + sizeof(bz_global)};
+        if (overlaps(g, span(mask, H, W, ld_mask, 1))) return BZ_ERR_ALIAS;
+        if (mean && (overlaps(g, span(mean, H, W, ld_ms, 4)) || overlaps(g, span(stdv, H, W, ld_ms, 4))))
+            return BZ_ERR_ALIAS;
+    }
+    j.rule = method;
+    memcpy(j.tp, p, sizeof(p));
+    j.gs = needs_stats ? (const GlobalStats *)stats : nullptr;
+    return run_box(j, (hipStream_t)stream);
+}
+
 bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w,
                              double q, uint8_t *Q, ptrdiff_t ld_Q, uint8_t *mask,
                              ptrdiff_t ld_mask, bz_stream stream)

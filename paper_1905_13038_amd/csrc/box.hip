@@ -227,6 +227,74 @@ __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S
     return (double)I < t;
 }
 
+// The other rules of Table 1, decided in binary64 for every pixel: m, s as
+// in below_reference, then the rule's threshold, each operation rounded once
+// (p: the rule's parameters; L, M, S: the image's minimum, mean and standard
+// deviation).  Wolf t = m - k (m - L)(1 - s/R); Feng t = a1 m
+// + k1 (s/R)^(1+g) (m - L) + k2 (s/R)^g L; Rais t = m + 0.3 (m s - M S) /
+// max{m s, M S} s (the fraction is 0 where both products are 0); Khurshid
+// (NICK) t = m + k sqrt(s^2 + m^2 (n-1)/n) with the clipped count n for h w;
+// Phansalkar t = m (1 + p e^(-q m) + k (s/R - 1)).
+__device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, uint32_t S2,
+                                                       int64_t n, int rule, double p0, double p1,
+                                                       double p2, double p3, double p4, double L,
+                                                       double M, double S)
+{
+#pragma clang fp contract(off)
+    const int64_t Vn = n * (int64_t)S2 - (int64_t)S1 * (int64_t)S1;
+    const double nd = (double)n;
+    const double m = (double)S1 / nd;
+    const double v = (double)Vn / (nd * nd);
+    const double s = __builtin_sqrt(v);
+    double t;
+    if (rule == T1_WOLF) {
+        double a = s / p1;
+        a = 1.0 - a;
+        double b = m - L;
+        b = p0 * b;
+        b = b * a;
+        t = m - b;
+    } else if (rule == T1_FENG) {
+        const double x = s / p4;
+        const double x1 = pow(x, 1.0 + p3);
+        const double x0 = pow(x, p3);
+        const double a = p0 * m;
+        double b = p1 * x1;
+        b = b * (m - L);
+        double c = p2 * x0;
+        c = c * L;
+        t = a + b;
+        t = t + c;
+    } else if (rule == T1_RAIS) {
+        const double a = m * s, b = M * S;
+        const double e = a > b ? a : b;
+        double f = 0.0;
+        if (e > 0.0) f = (a - b) / e;
+        double g = 0.3 * f;
+        g = g * s;
+        t = m + g;
+    } else if (rule == T1_NICK) {
+        const double a = s * s;
+        double b = m * m;
+        const double c = (nd - 1.0) / nd;
+        b = b * c;
+        const double r = __builtin_sqrt(a + b);
+        const double q = p0 * r;
+        t = m + q;
+    } else {  // T1_PHANSALKAR
+        double e = p1 * m;
+        e = exp(-e);
+        const double a = p0 * e;
+        double b = s / p3;
+        b = b - 1.0;
+        b = p2 * b;
+        double c = 1.0 + a;
+        c = c + b;
+        t = m * c;
+    }
+    return (double)I < t;
+}
+
 // Guard of the float32 decision: |t32 - t64| < 2^-18 * mag, where mag bounds
 // the magnitudes of the terms of t (m (|c1| s + |c0|) for Sauvola, m + |k| s
 // for Niblack).  With 1/n correctly rounded, n*S2 - S1^2 exact, a 1-ulp square
@@ -262,7 +330,7 @@ template <int MODE, bool AL, bool MS>
 __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
     constexpr int R = ROWS_PER_GROUP;
-    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK);
+    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK || MODE == MODE_TABLE1);
     const int NT = blockDim.x;
     const int PS = prefix_row_words(NT);
     const int BW = box_buffer_words(NT);
@@ -371,6 +439,13 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const float gA = (MODE == MODE_SAUVOLA)
                          ? -GUARD * __builtin_fmaf(__builtin_fabsf(a.c1), 127.5f, __builtin_fabsf(a.c0))
                          : -GUARD;
+    // Table 1 rules: the image's global minimum, mean and standard deviation
+    double gL = 0.0, gM = 0.0, gS = 0.0;
+    if (MODE == MODE_TABLE1 && a.gs != nullptr) {
+        gL = (double)a.gs->min;
+        gM = a.gs->mean;
+        gS = a.gs->stdev;
+    }
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
@@ -591,6 +666,15 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             }
             if (MODE == MODE_MEANSTD) continue;
             const uint32_t gw = gray_row(gs, r)[tid];  // byte k: column ec0 + 64 k (this lane's word)
+            if (MODE == MODE_TABLE1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    bits[r][k] = table1_below(byte_of(gw, k), c[k].S1, c[k].S2, (int64_t)c[k].n, a.rule,
+                                              a.tp[0], a.tp[1], a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
+                                     ? 1u
+                                     : 0u;
+                continue;
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 float d, nm;
@@ -602,7 +686,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         if (!need_i) return;
         // pixels within the guard: re-decided with the binary64 sequence
         // (rare; statistics recomputed from LDS, one call site)
-        if (a.force_ref || nmin < 0.0f) {
+        if (MODE != MODE_TABLE1 && (a.force_ref || nmin < 0.0f)) {
             uint32_t near = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -880,6 +964,7 @@ hipError_t launch_box(const BoxJob &a, hipStream_t stream)
     case MODE_MEANSTD: return launch_mode<MODE_MEANSTD, true>(a, stream);
     case MODE_SAUVOLA: return ms ? launch_mode<MODE_SAUVOLA, true>(a, stream) : launch_mode<MODE_SAUVOLA, false>(a, stream);
     case MODE_NIBLACK: return ms ? launch_mode<MODE_NIBLACK, true>(a, stream) : launch_mode<MODE_NIBLACK, false>(a, stream);
+    case MODE_TABLE1: return ms ? launch_mode<MODE_TABLE1, true>(a, stream) : launch_mode<MODE_TABLE1, false>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }

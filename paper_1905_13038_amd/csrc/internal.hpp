@@ -13,8 +13,22 @@ enum Mode : int {
     MODE_SUMS = 0,     // S1, S2 (uint32)
     MODE_MEANSTD = 1,  // m, s (float)
     MODE_SAUVOLA = 2,  // mask (+ optional m, s)
-    MODE_NIBLACK = 3   // mask (+ optional m, s)
+    MODE_NIBLACK = 3,  // mask (+ optional m, s)
+    MODE_TABLE1 = 4    // mask by one of Table 1's other rules, decided in binary64
+                       // (+ optional m, s)
 };
+
+// Table 1 rules of MODE_TABLE1 (the codes of the C ABI's bz_method).
+enum Table1 : int { T1_WOLF = 3, T1_FENG = 4, T1_RAIS = 5, T1_NICK = 6, T1_PHANSALKAR = 7 };
+
+// Global statistics of one image (layout of the C ABI's bz_global): exact
+// integer sums, then the mean and population standard deviation in binary64.
+struct GlobalStats {
+    uint64_t n, sum, sumsq;
+    uint32_t min, max;
+    double mean, stdev;
+};
+static_assert(sizeof(GlobalStats) == 48, "bz_global layout");
 
 // Columns owned by one lane in the box kernels (one dword of pixels).
 constexpr int COLS_PER_LANE = 4;
@@ -46,6 +60,11 @@ struct BoxJob {
     int strip, nsy;
     int aligned;           // all pointers/strides allow vector access
     int force_ref;         // decide every pixel with the binary64 sequence (testing)
+    // MODE_TABLE1: the rule, its parameters and the image's global statistics
+    // (device record; null for rules that use none)
+    int rule;
+    double tp[5];
+    const GlobalStats *gs;
 };
 
 // Fill o,u,l,r and the tiling of `job` (threads, tile_w, ntx, halo_l, strip,
@@ -78,6 +97,11 @@ int batch_variant(const BoxJob *jobs, int count);
 void register_batch_variant(const void *workspace, int variant);
 hipError_t launch_box_batched(void *workspace, hipStream_t stream);
 int batch_grid(int variant);
+
+// Global statistics of an image into a device record (three launches: reset,
+// accumulate, finish).
+hipError_t launch_global_stats(const uint8_t *I, int H, int W, int64_t ld, GlobalStats *out,
+                               hipStream_t stream);
 
 // Windowed quantile (Section 3.4).
 struct QuantJob {

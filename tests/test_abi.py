@@ -141,3 +141,48 @@ print(plan(A, item(0x110000, 0x210000, None, None)))             # disjoint: val
     out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
                          text=True, check=True)
     assert out.stdout.split() == ["3", "3", "3", "5", "5"]
+
+
+def test_validation_table1_and_global_stats(bz):
+    L = bz.lib
+    P5 = ctypes.c_double * 5
+    good = P5(0.5, 128.0, 0, 0, 0)
+    STATS = 0xC00000  # 8-byte aligned fake device record
+
+    def thr(method=3, params=good, stats=STATS, mask=OUT, mean=OUT2, std=OUT3, h=15):
+        return L.bz_threshold(IMG, 64, 64, 64, h, 15, method, params, stats, mask, 64, mean, std, 64, None)
+
+    assert thr(method=1) == 1                      # Sauvola/Niblack have their own calls
+    assert thr(method=8) == 1
+    assert thr(params=None) == 1                   # Wolf takes {k, R}
+    assert thr(params=P5(0.5, 0.0, 0, 0, 0)) == 1  # R > 0
+    assert thr(params=P5(float("nan"), 128.0, 0, 0, 0)) == 1
+    assert thr(stats=None) == 1                    # Wolf reads L
+    assert thr(stats=STATS + 4) == 1               # record alignment
+    assert thr(method=5, params=None, stats=OUT + 8) == 3   # Rais: record inside the mask
+    assert thr(method=4, params=P5(1, 0.2, 0.3, 2.0, -1.0)) == 1  # Feng's R
+    assert thr(method=7, params=P5(2.0, 0.04, 0.25, 0.0, 0)) == 1  # Phansalkar's R
+    assert thr(h=258) == 2
+    assert thr(mask=IMG + 10) == 3
+    assert L.bz_global_stats(None, 8, 8, 8, STATS, None) == 1
+    assert L.bz_global_stats(IMG, 8, 8, 8, STATS + 2, None) == 1
+    assert L.bz_global_stats(IMG, 8, 8, 8, IMG + 16, None) == 3
+
+
+def test_table1_valid_calls_reach_the_launch():
+    # NICK and Phansalkar need no record; Rais takes no parameters.  Valid
+    # calls pass validation (BZ_FAULT_INJECT=launch reports BZ_ERR_HIP there).
+    code = r'''
+import ctypes
+import paper_1905_13038_amd as b
+L = b.lib
+P5 = ctypes.c_double * 5
+print(L.bz_threshold(0x100000, 64, 64, 64, 15, 15, 6, P5(-0.1, 0, 0, 0, 0), None, 0x900000, 64, None, None, 0, None))
+print(L.bz_threshold(0x100000, 64, 64, 64, 15, 15, 7, P5(2.0, 0.04, 0.25, 128.0, 0), None, 0x900000, 64, None, None, 0, None))
+print(L.bz_threshold(0x100000, 64, 64, 64, 15, 15, 5, None, 0xC00000, 0x900000, 64, None, None, 0, None))
+print(L.bz_global_stats(0x100000, 64, 64, 64, 0xC00000, None))
+'''
+    env = dict(os.environ, BZ_FAULT_INJECT="launch")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
+                         text=True, check=True)
+    assert out.stdout.split() == ["5", "5", "5", "5"]

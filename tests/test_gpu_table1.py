@@ -1,0 +1,108 @@
+"""GPU parity of the other Table 1 rules (Wolf, Feng, Rais, Khurshid/NICK,
+Phansalkar) and of the global statistics they use, against the oracle.
+
+Wolf, Rais and NICK use only +, -, *, /, sqrt and max, which round the same
+way on both sides: their masks must be bit-exact.  Feng (pow) and Phansalkar
+(exp) call the device's and the C library's transcendental functions, which
+may differ in the last bit: their masks may disagree only where the oracle's
+|I - t| < 1e-4, and the count of such pixels is printed."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from docgen import gen_document
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-6
+NEAR = 1e-4
+
+CASES = {
+    "wolf": (oracle.WOLF, (0.5, 128.0), True),
+    "feng": (oracle.FENG, (0.9, 0.2, 0.3, 0.5, 128.0), False),
+    "rais": (oracle.RAIS, (), True),
+    "nick": (oracle.NICK, (-0.1,), True),
+    "phansalkar": (oracle.PHANSALKAR, (2.0, 0.04, 0.25, 128.0), False),
+}
+
+
+@pytest.fixture(scope="module")
+def bz():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1905_13038_amd as pkg
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check(bz, I, h, w, name, view=None, params=None):
+    code, p, exact = CASES[name]
+    p = p if params is None else params
+    print("table1", name, I.shape, h, w, p, flush=True)
+    mask, m, s = bz.table1_threshold(dev(I) if view is None else view, h, w, name, p)
+    torch.cuda.synchronize()
+    ref = oracle.table1(I, h, w, code, p)
+    got = mask.cpu().numpy()
+    bad = got != ref["mask"]
+    near = np.abs(I.astype(np.float64) - ref["t"]) < NEAR
+    print("  mask disagreements", int(bad.sum()), "oracle near-ties", int(near.sum()), flush=True)
+    if exact:
+        assert not bad.any()
+    else:
+        assert not (bad & ~near).any()
+    m = m.cpu().numpy().astype(np.float64)
+    s = s.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(m - ref["m"]) <= REL * np.abs(ref["m"]))
+    assert np.all(np.abs(s - ref["s"]) <= REL * np.abs(ref["s"]))
+
+
+@pytest.mark.parametrize("H,W", [(384, 512), (1, 1), (203, 301), (70, 4100)])
+def test_global_stats_match_oracle(bz, H, W):
+    I = gen_document(H, W, 80 + H, noise=10.0, stain=True)
+    g = bz.read_global_stats(bz.global_stats(dev(I)))
+    r = oracle.global_stats(I)
+    assert (g["n"], g["sum"], g["sumsq"]) == (r["N"], r["T1"], r["T2"])
+    assert (g["min"], g["max"]) == (r["L"], r["max"])
+    assert g["mean"] == r["M"] and g["std"] == r["S"]
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_small_page(bz, name):
+    check(bz, gen_document(384, 512, 1, noise=10.0, stain=True), 31, 31, name)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_ragged_strided_page(bz, name):
+    # odd sizes, a window wider than tall, rows at an odd stride and offset
+    I = gen_document(203, 301, 5, noise=10.0, stain=True)
+    big = torch.zeros((203, 311), dtype=torch.uint8, device="cuda")
+    big[:, 3:304] = dev(I)
+    check(bz, I, 9, 40, name, view=big[:, 3:304])
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_headline_page_w75(bz, name):
+    check(bz, gen_document(3072, 4096, 2, noise=10.0, stain=True), 75, 75, name)
+
+
+def test_feng_integer_exponent_and_constant_image(bz):
+    # gamma = 2: powers of s/R; a constant image: s = 0 and S = 0 everywhere
+    check(bz, gen_document(120, 160, 7, noise=10.0, stain=True), 15, 15, "feng",
+          params=(0.85, 0.15, 0.05, 2.0, 128.0))
+    C = np.full((40, 50), 133, np.uint8)
+    for name in sorted(CASES):
+        check(bz, C, 7, 9, name)
+
+
+def test_global_record_is_reused(bz):
+    # a record computed once serves several calls; outputs equal the
+    # call that computes its own record
+    I = dev(gen_document(200, 260, 9, noise=10.0, stain=True))
+    rec = bz.global_stats(I)
+    a = bz.table1_threshold(I, 21, 21, "wolf", (0.4, 100.0), stats=rec)
+    b = bz.table1_threshold(I, 21, 21, "wolf", (0.4, 100.0))
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
