@@ -19,6 +19,7 @@ threshold, one thread) on the same page.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -302,6 +303,32 @@ def extras(sets, host, args):
         return res
 
     warm_gpu(lambda i: page_call("sauvola", 75, True, i))
+    def table1():
+        # the other rules of Table 1 on the headline page (w = 75), mask + mean
+        # + std, with the page's global-statistics record computed once
+        rules = {"wolf": (0.5, 128.0), "feng": (0.9, 0.2, 0.3, 0.5, 128.0), "rais": (),
+                 "nick": (-0.1,), "phansalkar": (2.0, 0.04, 0.25, 128.0)}
+        recs = [bz.global_stats(s_[0]) for s_ in sets]
+        res = {}
+        g_us = _loop_us(lambda i: lib.bz_global_stats(sets[i % len(sets)][0].data_ptr(), H, W, W,
+                                                      recs[i % len(sets)].data_ptr(), st), 20)
+        res["global_stats"] = {"us": round(g_us, 2), "GB_s": round(px / g_us / 1e3, 1)}
+        for name, p in rules.items():
+            code = bz.TABLE1[name][0]
+            pv = (ctypes.c_double * 5)(*(list(p) + [0.0] * (5 - len(p))))
+
+            def f(i, code=code, pv=pv):
+                img, mask, m, sd = sets[i % len(sets)]
+                rc = lib.bz_threshold(img.data_ptr(), H, W, W, 75, 75, code, pv,
+                                      recs[i % len(sets)].data_ptr(), mask.data_ptr(), W, m.data_ptr(),
+                                      sd.data_ptr(), W, st)
+                if rc != 0:
+                    raise RuntimeError("status %d" % rc)
+            us = _loop_us(f, 20)
+            res[name] = {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1),
+                         "hbm_frac": round(10.0 * px / us / 1e3 / HBM_PEAK_GBS, 4)}
+        return res
+
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
     guarded("mean_std_w75", mean_std)
@@ -310,6 +337,7 @@ def extras(sets, host, args):
     guarded("ragged_batch_256", batch)
     guarded("soft_fwd_bwd_32x1024x1024_h32", soft)
     guarded("quantile_2048x1536", quantiles)
+    guarded("table1_4096x3072_w75", table1)
     return out
 
 

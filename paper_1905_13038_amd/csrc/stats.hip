@@ -5,8 +5,9 @@
 //
 // Three launches, all graph-capturable (no memset): a one-lane reset of the
 // record, a grid of workgroups that each reduce a set of rows in registers
-// and fold their totals into the record with integer atomics (order-free, so
-// the result is deterministic), and a one-lane finish.
+// and LDS and fold their totals into the record with one integer atomic per
+// statistic (order-free, so the result is deterministic), and a one-lane
+// finish.
 #include "internal.hpp"
 
 #include <math.h>
@@ -15,7 +16,7 @@ namespace bz {
 namespace {
 
 constexpr int STATS_THREADS = 256;
-constexpr int STATS_MAX_BLOCKS = 1024;
+constexpr int STATS_MAX_BLOCKS = 256;  // one per CU: few atomics on the record
 
 __global__ void k_gstats_reset(GlobalStats *g)
 {
@@ -46,28 +47,63 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
-// Workgroup b takes rows b, b + gridDim.x, ...; its lanes stride the columns.
-// Per-lane sums stay below 2^64 (at most 2^46 pixels of at most 255^2).
+// Workgroup b takes rows b, b + gridDim.x, ...; its lanes stride the columns,
+// four gray levels per dword load when rows allow it (AL), else one byte.
+// Per-lane sums stay below 2^64 (at most 2^46 pixels of at most 255^2).  The
+// four waves of a workgroup combine through LDS, so each workgroup issues one
+// atomic per statistic.
+template <bool AL>
 __global__ __launch_bounds__(STATS_THREADS) void k_gstats_acc(const uint8_t *I, int H, int W, int64_t ld,
                                                              GlobalStats *g)
 {
+    __shared__ uint64_t ws[2][STATS_THREADS / 64];
+    __shared__ uint32_t wm[2][STATS_THREADS / 64];
     uint64_t s = 0, q = 0;
     uint32_t lo = 255u, hi = 0u;
     for (int y = blockIdx.x; y < H; y += gridDim.x) {
         const uint8_t *row = I + (int64_t)y * ld;
-        for (int x = threadIdx.x; x < W; x += STATS_THREADS) {
-            const uint32_t v = row[x];
-            s += v;
-            q += v * v;
-            lo = min(lo, v);
-            hi = max(hi, v);
+        if (AL) {
+            const uint32_t *r4 = (const uint32_t *)row;
+            for (int x = threadIdx.x; 4 * x < W; x += STATS_THREADS) {
+                const uint32_t d = r4[x];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t v = (d >> (8 * b)) & 0xffu;
+                    s += v;
+                    q += v * v;
+                    lo = min(lo, v);
+                    hi = max(hi, v);
+                }
+            }
+        } else {
+            for (int x = threadIdx.x; x < W; x += STATS_THREADS) {
+                const uint32_t v = row[x];
+                s += v;
+                q += v * v;
+                lo = min(lo, v);
+                hi = max(hi, v);
+            }
         }
     }
     s = wave_sum_u64(s);
     q = wave_sum_u64(q);
     lo = wave_min_u32(lo);
     hi = wave_max_u32(hi);
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        ws[0][wave] = s;
+        ws[1][wave] = q;
+        wm[0][wave] = lo;
+        wm[1][wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < STATS_THREADS / 64; ++i) {
+            s += ws[0][i];
+            q += ws[1][i];
+            lo = min(lo, wm[0][i]);
+            hi = max(hi, wm[1][i]);
+        }
         atomicAdd((unsigned long long *)&g->sum, (unsigned long long)s);
         atomicAdd((unsigned long long *)&g->sumsq, (unsigned long long)q);
         atomicMin(&g->min, lo);
@@ -95,7 +131,11 @@ hipError_t launch_global_stats(const uint8_t *I, int H, int W, int64_t ld, Globa
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int blocks = H < STATS_MAX_BLOCKS ? H : STATS_MAX_BLOCKS;
-    hipLaunchKernelGGL(k_gstats_acc, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
+    const bool al = ((uintptr_t)I % 4 == 0) && (ld % 4 == 0) && (W % 4 == 0);
+    if (al)
+        hipLaunchKernelGGL(k_gstats_acc<true>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
+    else
+        hipLaunchKernelGGL(k_gstats_acc<false>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gstats_finish, dim3(1), dim3(1), 0, stream, out, (uint64_t)H * (uint64_t)W);
