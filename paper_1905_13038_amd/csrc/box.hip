@@ -295,6 +295,82 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
     return (double)I < t;
 }
 
+// Float32 form of a Table 1 rule and its guard.  With m and s within 2 and 3
+// units of 2^-24 (u) of their values, first-order error bounds of the float32
+// threshold against the binary64 one, relative to the magnitude mag of its
+// terms, are about: Wolf 12u, NICK 7u, Rais 25u, Phansalkar (13 + 4|q m|)u
+// of |m| C with C = 1 + |p| e^(-qm) + |k|(1 + s/R), and Feng
+// (9 + 5 (1 + |g|))u.  The guard G mag takes 2^-18 (64u) for Wolf and NICK,
+// 2^-17 for Phansalkar (mag scaled by 1 + |q m|), 2^-16 for Rais and 2^-15
+// for Feng (mag scaled by 2 + |g|): a factor of 5 or more over the bounds.
+// Where |I - t32| > G mag the float32 and binary64 decisions agree; other
+// pixels, and any non-finite value, go to table1_below.
+struct T1Fast {
+    int rule;
+    float p0, p1, p2, p3;
+    float rR;   // 1/R
+    float L;    // global minimum
+    float MS;   // M S
+    float G;    // guard factor
+};
+
+__device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, double L, double M, double S)
+{
+    T1Fast f;
+    f.rule = rule;
+    f.p0 = (float)tp[0];
+    f.p1 = (float)tp[1];
+    f.p2 = (float)tp[2];
+    f.p3 = (float)tp[3];
+    const double R = rule == T1_WOLF ? tp[1] : rule == T1_FENG ? tp[4] : rule == T1_PHANSALKAR ? tp[3] : 1.0;
+    f.rR = (float)(1.0 / R);
+    f.L = (float)L;
+    f.MS = (float)M * (float)S;
+    f.G = rule == T1_WOLF || rule == T1_NICK ? 0x1p-18f
+          : rule == T1_PHANSALKAR             ? 0x1p-17f
+          : rule == T1_RAIS                   ? 0x1p-16f
+                                              : 0x1p-15f;
+    return f;
+}
+
+// d = I - t32 and the guard g = G mag: the float32 decision is the sign of d,
+// valid where |d| > g.
+__device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, float rn, float I,
+                                            float &d, float &g)
+{
+    float t, mag;
+    if (f.rule == T1_WOLF) {
+        const float a = 1.0f - s * f.rR;
+        const float b = f.p0 * (m - f.L);
+        t = m - b * a;
+        mag = fabsf(m) + fabsf(f.p0) * (fabsf(m) + fabsf(f.L)) * (1.0f + s * f.rR);
+    } else if (f.rule == T1_NICK) {
+        const float r = sqrtf(fmaf(s, s, m * m * (1.0f - rn)));
+        t = fmaf(f.p0, r, m);
+        mag = fabsf(m) + fabsf(f.p0) * r;
+    } else if (f.rule == T1_RAIS) {
+        const float a = m * s;
+        const float e = fmaxf(a, f.MS);
+        const float q = e > 0.0f ? (a - f.MS) / e : 0.0f;
+        t = fmaf(0.3f * s, q, m);
+        mag = fabsf(m) + 0.3f * s;
+    } else if (f.rule == T1_PHANSALKAR) {
+        const float qm = f.p1 * m;
+        const float ex = expf(-qm);
+        const float c = 1.0f + f.p0 * ex + f.p2 * (s * f.rR - 1.0f);
+        t = m * c;
+        mag = fabsf(m) * (1.0f + fabsf(f.p0) * ex + fabsf(f.p2) * (1.0f + s * f.rR)) * (1.0f + fabsf(qm));
+    } else {  // T1_FENG
+        const float x = s * f.rR;
+        const float x1 = powf(x, 1.0f + f.p3), x0 = powf(x, f.p3);
+        t = f.p0 * m + f.p1 * x1 * (m - f.L) + f.p2 * x0 * f.L;
+        mag = (fabsf(f.p0 * m) + fabsf(f.p1) * x1 * (fabsf(m) + fabsf(f.L)) + fabsf(f.p2) * x0 * fabsf(f.L)) *
+              (2.0f + fabsf(f.p3));
+    }
+    d = I - t;
+    g = f.G * mag;
+}
+
 // Guard of the float32 decision: |t32 - t64| < 2^-18 * mag, where mag bounds
 // the magnitudes of the terms of t (m (|c1| s + |c0|) for Sauvola, m + |k| s
 // for Niblack).  With 1/n correctly rounded, n*S2 - S1^2 exact, a 1-ulp square
@@ -446,6 +522,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         gM = a.gs->mean;
         gS = a.gs->stdev;
     }
+    const T1Fast t1f = t1_fast_params(a.rule, a.tp, gL, gM, gS);
 
     // ---- priming: column sums over rows y0-o .. y0+u-1 ----
     uint32_t C[4] = {0, 0, 0, 0}, D[4] = {0, 0, 0, 0};
@@ -590,7 +667,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     struct ColStats {
         uint32_t S1, S2;
         double n;
-        float m, s;
+        float m, s, rn;
     };
     auto col_stats = [&](int b, int r, int k, int y, bool interior) -> ColStats {
         ColStats c;
@@ -609,6 +686,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             c.n = (double)nr * (double)nc;
             rn = 1.0f / (float)c.n;
         }
+        c.rn = rn;
         c.m = (float)c.S1 * rn;
         const double s1d = (double)c.S1;
         const double vn = __builtin_fma(c.n, (double)c.S2, -(s1d * s1d));
@@ -635,6 +713,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         constexpr bool interior = decltype(interior_tag)::value;
         uint32_t bits[R][4];
         float nmin = 1.0f;
+        uint32_t t1near = 0;  // Table 1: pixels inside the float32 guard
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = yg + r;
@@ -668,11 +747,12 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             const uint32_t gw = gray_row(gs, r)[tid];  // byte k: column ec0 + 64 k (this lane's word)
             if (MODE == MODE_TABLE1) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    bits[r][k] = table1_below(byte_of(gw, k), c[k].S1, c[k].S2, (int64_t)c[k].n, a.rule,
-                                              a.tp[0], a.tp[1], a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
-                                     ? 1u
-                                     : 0u;
+                for (int k = 0; k < 4; ++k) {
+                    float d, g;
+                    table1_fast(t1f, c[k].m, c[k].s, c[k].rn, (float)byte_of(gw, k), d, g);
+                    bits[r][k] = d < 0.0f ? 1u : 0u;
+                    if (a.force_ref || !(fabsf(d) > g)) t1near |= 1u << (4 * r + k);
+                }
                 continue;
             }
 #pragma unroll
@@ -686,7 +766,25 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         if (!need_i) return;
         // pixels within the guard: re-decided with the binary64 sequence
         // (rare; statistics recomputed from LDS, one call site)
-        if (MODE != MODE_TABLE1 && (a.force_ref || nmin < 0.0f)) {
+        if (MODE == MODE_TABLE1) {
+            // pixels inside the guard: the binary64 sequence (statistics
+            // recomputed from LDS)
+            while (t1near != 0) {
+                const int i = __builtin_ctz(t1near);
+                t1near &= t1near - 1;
+                const int r = i >> 2, k = i & 3;
+                const ColStats c = col_stats(b, r, k, yg + r, false);
+                const uint32_t gv = ((const uint8_t *)gray_row(gs, r))[4 * tid + k];
+                const uint32_t bit = table1_below(gv, c.S1, c.S2, (int64_t)c.n, a.rule, a.tp[0], a.tp[1],
+                                                  a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
+                                         ? 1u
+                                         : 0u;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) bits[rr][kk] = (i == 4 * rr + kk) ? bit : bits[rr][kk];
+            }
+        } else if (a.force_ref || nmin < 0.0f) {
             uint32_t near = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {

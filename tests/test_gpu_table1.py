@@ -106,3 +106,17 @@ def test_global_record_is_reused(bz):
     a = bz.table1_threshold(I, 21, 21, "wolf", (0.4, 100.0), stats=rec)
     b = bz.table1_threshold(I, 21, 21, "wolf", (0.4, 100.0))
     assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_guarded_float32_path_equals_binary64_everywhere(bz, monkeypatch, name):
+    # BZ_FORCE_REFERENCE=1 decides every pixel with the binary64 sequence;
+    # the default path decides in float32 outside the guard: same masks
+    I = dev(gen_document(600, 800, 12, noise=10.0, stain=True))
+    code, p, _ = CASES[name]
+    rec = bz.global_stats(I)
+    fast = bz.table1_threshold(I, 45, 45, name, p, stats=rec)
+    monkeypatch.setenv("BZ_FORCE_REFERENCE", "1")
+    ref = bz.table1_threshold(I, 45, 45, name, p, stats=rec)
+    torch.cuda.synchronize()
+    assert torch.equal(fast[0], ref[0])
