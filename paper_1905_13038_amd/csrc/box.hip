@@ -300,7 +300,7 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
 // threshold against the binary64 one, relative to the magnitude mag of its
 // terms, are about: Wolf 12u, NICK 7u, Rais 25u, Phansalkar (13 + 4|q m|)u
 // of |m| C with C = 1 + |p| e^(-qm) + |k|(1 + s/R), and Feng
-// (9 + 5 (1 + |g|))u.  The guard G mag takes 2^-18 (64u) for Wolf and NICK,
+// (10 + 5 |g|)u (one powf, x^(1+g) = x x^g).  The guard G mag takes 2^-18 (64u) for Wolf and NICK,
 // 2^-17 for Phansalkar (mag scaled by 1 + |q m|), 2^-16 for Rais and 2^-15
 // for Feng (mag scaled by 2 + |g|): a factor of 5 or more over the bounds.
 // Where |I - t32| > G mag the float32 and binary64 decisions agree; other
@@ -362,7 +362,7 @@ __device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, f
         mag = fabsf(m) * (1.0f + fabsf(f.p0) * ex + fabsf(f.p2) * (1.0f + s * f.rR)) * (1.0f + fabsf(qm));
     } else {  // T1_FENG
         const float x = s * f.rR;
-        const float x1 = powf(x, 1.0f + f.p3), x0 = powf(x, f.p3);
+        const float x0 = powf(x, f.p3), x1 = x * x0;  // x^(1+g) = x x^g
         t = f.p0 * m + f.p1 * x1 * (m - f.L) + f.p2 * x0 * f.L;
         mag = (fabsf(f.p0 * m) + fabsf(f.p1) * x1 * (fabsf(m) + fabsf(f.L)) + fabsf(f.p2) * x0 * fabsf(f.L)) *
               (2.0f + fabsf(f.p3));
