@@ -52,7 +52,21 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 // Per-lane sums stay below 2^64 (at most 2^46 pixels of at most 255^2).  The
 // four waves of a workgroup combine through LDS, so each workgroup issues one
 // atomic per statistic.
-template <bool AL>
+__device__ __forceinline__ void add_word(uint32_t d, uint64_t &s, uint64_t &q, uint32_t &lo, uint32_t &hi)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t v = (d >> (8 * b)) & 0xffu;
+        s += v;
+        q += v * v;
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+}
+
+// AL: 0 bytes, 1 dwords (rows 4-byte aligned, W % 4 == 0), 2 16-byte vectors
+// (rows 16-byte aligned, W % 16 == 0) with the loads of four rows in flight.
+template <int AL>
 __global__ __launch_bounds__(STATS_THREADS) void k_gstats_acc(const uint8_t *I, int H, int W, int64_t ld,
                                                              GlobalStats *g)
 {
@@ -60,9 +74,38 @@ __global__ __launch_bounds__(STATS_THREADS) void k_gstats_acc(const uint8_t *I, 
     __shared__ uint32_t wm[2][STATS_THREADS / 64];
     uint64_t s = 0, q = 0;
     uint32_t lo = 255u, hi = 0u;
-    for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    int y = blockIdx.x;
+    if (AL == 2) {
+        constexpr int U = 4;
+        for (; y + (U - 1) * (int)gridDim.x < H; y += U * gridDim.x) {
+            for (int x = threadIdx.x; 16 * x < W; x += STATS_THREADS) {
+                uint4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = ((const uint4 *)(I + (int64_t)(y + u * gridDim.x) * ld))[x];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    add_word(v[u].x, s, q, lo, hi);
+                    add_word(v[u].y, s, q, lo, hi);
+                    add_word(v[u].z, s, q, lo, hi);
+                    add_word(v[u].w, s, q, lo, hi);
+                }
+            }
+        }
+        for (; y < H; y += gridDim.x) {
+            const uint4 *r16 = (const uint4 *)(I + (int64_t)y * ld);
+            for (int x = threadIdx.x; 16 * x < W; x += STATS_THREADS) {
+                const uint4 v = r16[x];
+                add_word(v.x, s, q, lo, hi);
+                add_word(v.y, s, q, lo, hi);
+                add_word(v.z, s, q, lo, hi);
+                add_word(v.w, s, q, lo, hi);
+            }
+        }
+    }
+    for (; AL != 2 && y < H; y += gridDim.x) {
         const uint8_t *row = I + (int64_t)y * ld;
-        if (AL) {
+        if (AL == 1) {
             const uint32_t *r4 = (const uint32_t *)row;
             for (int x = threadIdx.x; 4 * x < W; x += STATS_THREADS) {
                 const uint32_t d = r4[x];
@@ -131,11 +174,14 @@ hipError_t launch_global_stats(const uint8_t *I, int H, int W, int64_t ld, Globa
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int blocks = H < STATS_MAX_BLOCKS ? H : STATS_MAX_BLOCKS;
-    const bool al = ((uintptr_t)I % 4 == 0) && (ld % 4 == 0) && (W % 4 == 0);
-    if (al)
-        hipLaunchKernelGGL(k_gstats_acc<true>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
+    const bool al4 = ((uintptr_t)I % 4 == 0) && (ld % 4 == 0) && (W % 4 == 0);
+    const bool al16 = ((uintptr_t)I % 16 == 0) && (ld % 16 == 0) && (W % 16 == 0);
+    if (al16)
+        hipLaunchKernelGGL(k_gstats_acc<2>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
+    else if (al4)
+        hipLaunchKernelGGL(k_gstats_acc<1>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
     else
-        hipLaunchKernelGGL(k_gstats_acc<false>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
+        hipLaunchKernelGGL(k_gstats_acc<0>, dim3(blocks), dim3(STATS_THREADS), 0, stream, I, H, W, ld, out);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gstats_finish, dim3(1), dim3(1), 0, stream, out, (uint64_t)H * (uint64_t)W);

@@ -60,7 +60,7 @@ def check(bz, I, h, w, name, view=None, params=None):
     assert np.all(np.abs(s - ref["s"]) <= REL * np.abs(ref["s"]))
 
 
-@pytest.mark.parametrize("H,W", [(384, 512), (1, 1), (203, 301), (70, 4100)])
+@pytest.mark.parametrize("H,W", [(384, 512), (1, 1), (203, 301), (70, 4100), (1000, 512), (3072, 4096)])
 def test_global_stats_match_oracle(bz, H, W):
     I = gen_document(H, W, 80 + H, noise=10.0, stain=True)
     g = bz.read_global_stats(bz.global_stats(dev(I)))
