@@ -208,6 +208,21 @@ def niblack(I, h, w, k=-0.2, **kw):
     return threshold(I, h, w, NIBLACK, k, 128.0, **kw)
 
 
+def bernsen(I, h: int, w: int, contrast_min: int):
+    """Bernsen's rule on the window extremes (the paper cites it as the
+    midrange method computed from local minima and maxima): mn, mx = the
+    clipped window's minimum and maximum (the quantiles q = 0 and q = 1);
+    mask = 1 where mx - mn >= contrast_min and I lies below the midrange,
+    2 I < mn + mx (exact in integers); windows of lower contrast are
+    background (mask 0).  Returns (mask, mn, mx)."""
+    mn, _ = quantile_hist(I, h, w, 0.0)
+    mx, _ = quantile_hist(I, h, w, 1.0)
+    Ii = np.asarray(I).astype(np.int32)
+    lo, hi = mn.astype(np.int32), mx.astype(np.int32)
+    mask = ((hi - lo >= int(contrast_min)) & (2 * Ii < lo + hi)).astype(np.uint8)
+    return mask, mn, mx
+
+
 def global_stats(I):
     """Table 1's global statistics of the whole image: dict(L, max, M, S, N,
     T1, T2) with L the minimum gray level, M the mean and S the population

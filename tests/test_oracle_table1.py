@@ -2,7 +2,8 @@
 Khurshid/NICK, Phansalkar) and of the global statistics L, M, S they use:
 NumPy's own statistics, each method's formula evaluated in another algebraic
 form from brute-force window sums, and the special cases where a method
-reduces to Sauvola or to the window mean."""
+reduces to Sauvola or to the window mean; and of Bernsen's midrange rule on
+the window extremes, by brute force over clipped windows."""
 import numpy as np
 import pytest
 
@@ -151,3 +152,28 @@ def test_table1_t_scalar_matches_image_routine():
         for (i, j) in [(0, 0), (10, 12), (19, 24)]:
             t = oracle.table1_t(method, r["m"][i, j], r["s"][i, j], float(n[i, j]), p, g["L"], g["M"], g["S"])
             assert t == r["t"][i, j]
+
+
+def test_bernsen_brute_force():
+    # tiny images: the window extremes by explicit loops over clipped windows
+    rng = np.random.default_rng(5)
+    for (H, W, h, w, c) in [(7, 9, 3, 4, 15), (5, 5, 6, 2, 0), (11, 6, 5, 5, 100), (1, 8, 1, 3, 1)]:
+        I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        o, u, l, r = (h + 1) // 2, h // 2, (w + 1) // 2, w // 2
+        mask, mn, mx = oracle.bernsen(I, h, w, c)
+        for i in range(H):
+            for j in range(W):
+                blk = I[max(i - o + 1, 0):min(i + u, H - 1) + 1, max(j - l + 1, 0):min(j + r, W - 1) + 1]
+                lo, hi = int(blk.min()), int(blk.max())
+                assert (mn[i, j], mx[i, j]) == (lo, hi)
+                want = 1 if (hi - lo >= c and I[i, j] < (lo + hi) / 2) else 0
+                assert mask[i, j] == want
+
+
+def test_bernsen_low_contrast_windows_are_background():
+    I = np.full((20, 30), 120, np.uint8)
+    I[5:8, 10:13] = 126       # contrast 6 somewhere
+    mask, mn, mx = oracle.bernsen(I, 7, 7, 7)
+    assert not mask.any()
+    mask, mn, mx = oracle.bernsen(I, 7, 7, 6)
+    assert mask.any() and not mask[I == 126].any()
