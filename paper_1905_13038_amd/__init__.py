@@ -21,7 +21,8 @@ import torch
 __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
     "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola",
-    "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "LIB_PATH",
+    "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "window_minmax", "bernsen",
+    "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbinarize.so")
@@ -53,6 +54,10 @@ lib.bz_niblack.restype = _I
 lib.bz_niblack.argtypes = [_P, _I, _I, _PD, _I, _I, _F, _P, _PD, _P, _P, _PD, _P]
 lib.bz_window_quantile.restype = _I
 lib.bz_window_quantile.argtypes = [_P, _I, _I, _PD, _I, _I, _D, _P, _PD, _P, _PD, _P]
+lib.bz_window_minmax.restype = _I
+lib.bz_window_minmax.argtypes = [_P, _I, _I, _PD, _I, _I, _P, _P, _PD, _P]
+lib.bz_bernsen.restype = _I
+lib.bz_bernsen.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _P, _PD, _P]
 lib.bz_global_stats.restype = _I
 lib.bz_global_stats.argtypes = [_P, _I, _I, _PD, _P, _P]
 lib.bz_threshold.restype = _I
@@ -308,6 +313,29 @@ def sauvola_batched(images, params, strips=None):
     plan = BatchPlan(images, params, strips)
     plan.run()
     return plan.outputs()
+
+
+def window_minmax(img: torch.Tensor, h: int, w: int):
+    """Minimum and maximum of each pixel's clipped window (uint8, exact).
+    Returns (mn, mx)."""
+    img, H, W, ld = _image(img)
+    mn = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    mx = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    _check(lib.bz_window_minmax(img.data_ptr(), H, W, ld, h, w, mn.data_ptr(), mx.data_ptr(), W,
+                                _stream(img)), "bz_window_minmax")
+    return mn, mx
+
+
+def bernsen(img: torch.Tensor, h: int, w: int, contrast_min: int = 15):
+    """Bernsen's midrange rule: mask = 1 where the window's range reaches
+    ``contrast_min`` and 2 I < min + max.  Returns (mask, mn, mx)."""
+    img, H, W, ld = _image(img)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    mn = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    mx = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    _check(lib.bz_bernsen(img.data_ptr(), H, W, ld, h, w, int(contrast_min), mask.data_ptr(), W,
+                          mn.data_ptr(), mx.data_ptr(), W, _stream(img)), "bz_bernsen")
+    return mask, mn, mx
 
 
 # The other rules of Table 1: C-ABI code and parameter names, in order.

@@ -360,6 +360,76 @@ bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
     return hip_status(launch_quantile(j, (hipStream_t)stream));
 }
 
+namespace {
+QuantJob quantile_job(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, double q, uint8_t *Q,
+                      ptrdiff_t ld_Q)
+{
+    QuantJob j;
+    memset(&j, 0, sizeof(j));
+    j.I = I;
+    j.ldI = ld_I;
+    j.H = H;
+    j.W = W;
+    j.h = h;
+    j.w = w;
+    j.o = (h + 1) / 2;
+    j.u = h / 2;
+    j.l = (w + 1) / 2;
+    j.r = w / 2;
+    j.q = q;
+    j.Q = Q;
+    j.ldQ = ld_Q;
+    return j;
+}
+
+// Validate the extremes outputs (and the mask, when given) of a min/max call.
+bz_status check_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
+                       uint8_t *mx, ptrdiff_t ld_out, uint8_t *mask, ptrdiff_t ld_mask)
+{
+    bz_status st = check_image(I, H, W, ld_I, h, w);
+    if (st != BZ_OK) return st;
+    if ((st = check_out(mn, H, W, ld_out, 1)) != BZ_OK) return st;
+    if ((st = check_out(mx, H, W, ld_out, 1)) != BZ_OK) return st;
+    const Range in = span(I, H, W, ld_I, 1), a = span(mn, H, W, ld_out, 1), b = span(mx, H, W, ld_out, 1);
+    if (overlaps(in, a) || overlaps(in, b) || overlaps(a, b)) return BZ_ERR_ALIAS;
+    if (mask) {
+        if ((st = check_out(mask, H, W, ld_mask, 1)) != BZ_OK) return st;
+        const Range m = span(mask, H, W, ld_mask, 1);
+        if (overlaps(in, m) || overlaps(a, m) || overlaps(b, m)) return BZ_ERR_ALIAS;
+    }
+    return BZ_OK;
+}
+}  // namespace
+
+bz_status bz_window_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
+                           uint8_t *mx, ptrdiff_t ld_out, bz_stream stream)
+{
+    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_out, nullptr, 0);
+    if (st != BZ_OK) return st;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    hipError_t e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 0.0, mn, ld_out), (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 1.0, mx, ld_out), (hipStream_t)stream);
+    return hip_status(e);
+}
+
+bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int contrast_min,
+                     uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
+                     bz_stream stream)
+{
+    if (mask == nullptr) return BZ_ERR_INVALID;
+    if (contrast_min < 0 || contrast_min > 256) return BZ_ERR_INVALID;
+    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_mm, mask, ld_mask);
+    if (st != BZ_OK) return st;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    hipError_t e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 0.0, mn, ld_mm), (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 1.0, mx, ld_mm), (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_bernsen(I, ld_I, mn, mx, ld_mm, H, W, contrast_min, mask, ld_mask, (hipStream_t)stream);
+    return hip_status(e);
+}
+
 size_t bz_batched_workspace_size(int count)
 {
     if (count < 0) return 0;

@@ -186,3 +186,16 @@ print(L.bz_global_stats(0x100000, 64, 64, 64, 0xC00000, None))
     out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
                          text=True, check=True)
     assert out.stdout.split() == ["5", "5", "5", "5"]
+
+
+def test_validation_minmax_and_bernsen(bz):
+    L = bz.lib
+    MN, MX = 0xD00000, 0xE00000
+    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, MN, MN + 64, 64, None) == 3   # mn, mx overlap
+    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, IMG + 5, MX, 64, None) == 3
+    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 300, MN, MX, 64, None) == 2
+    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, None, MX, 64, None) == 1
+    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 15, None, 64, MN, MX, 64, None) == 1
+    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, -1, OUT, 64, MN, MX, 64, None) == 1
+    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 257, OUT, 64, MN, MX, 64, None) == 1
+    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 15, MN + 3, 64, MN, MX, 64, None) == 3

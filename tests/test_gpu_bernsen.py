@@ -1,0 +1,46 @@
+"""GPU parity of the window extremes and Bernsen's midrange rule against the
+oracle (bit-exact: everything is integer)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from docgen import gen_document
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bz():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1905_13038_amd as pkg
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("H,W,h,w,c", [(384, 512, 31, 31, 15), (203, 301, 9, 40, 20), (1, 1, 3, 3, 0),
+                                       (70, 4100, 15, 5, 30), (100, 90, 257, 257, 15), (64, 64, 1, 1, 0),
+                                       (1536, 2048, 32, 32, 15)])
+def test_bernsen_matches_oracle(bz, H, W, h, w, c):
+    I = gen_document(H, W, 90 + H, noise=10.0, stain=True)
+    print("bernsen", H, W, h, w, c, flush=True)
+    mask, mn, mx = bz.bernsen(dev(I), h, w, c)
+    torch.cuda.synchronize()
+    rmask, rmn, rmx = oracle.bernsen(I, h, w, c)
+    assert np.array_equal(mn.cpu().numpy(), rmn)
+    assert np.array_equal(mx.cpu().numpy(), rmx)
+    assert np.array_equal(mask.cpu().numpy(), rmask)
+
+
+def test_minmax_strided_view(bz):
+    I = gen_document(150, 211, 4, noise=10.0, stain=True)
+    big = torch.zeros((150, 230), dtype=torch.uint8, device="cuda")
+    big[:, 7:218] = dev(I)
+    mn, mx = bz.window_minmax(big[:, 7:218], 11, 6)
+    torch.cuda.synchronize()
+    _, rmn, rmx = oracle.bernsen(I, 11, 6, 0)
+    assert np.array_equal(mn.cpu().numpy(), rmn) and np.array_equal(mx.cpu().numpy(), rmx)
