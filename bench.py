@@ -300,14 +300,16 @@ def extras(sets, host, args):
                 npx = Hq * Wq
                 res["h%d_q%g" % (win, q)] = {"us": round(us, 1), "Gpix_s": round(npx / us / 1e3, 2),
                                             "G_updates_s": round(2.0 * win * npx / us / 1e3, 1)}
-        # Bernsen's rule: the window extremes (quantiles q = 0 and 1) and the
-        # elementwise midrange decision
+        # Bernsen's rule: the window extremes (two separable passes) and the
+        # midrange decision
         mn = torch.empty_like(img)
         mx = torch.empty_like(img)
+        nb = int(lib.bz_extremes_workspace_size(Hq, Wq))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
 
         def b(i):
             rc = lib.bz_bernsen(img.data_ptr(), Hq, Wq, Wq, 32, 32, 15, mk.data_ptr(), Wq, mn.data_ptr(),
-                                mx.data_ptr(), Wq, st)
+                                mx.data_ptr(), Wq, ws.data_ptr(), nb, st)
             if rc != 0:
                 raise RuntimeError("status %d" % rc)
         us = _loop_us(b, 10)

@@ -113,24 +113,31 @@ bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
                              double q, uint8_t *Q, ptrdiff_t ld_Q, uint8_t *mask,
                              ptrdiff_t ld_mask, bz_stream stream);
 
+/* Workspace bytes of bz_window_minmax and bz_bernsen for an H x W image. */
+size_t bz_extremes_workspace_size(int H, int W);
+
 /*
  * Window minimum and maximum of the clipped window (in-bounds pixels only;
- * the paper's local extremes, computed as the quantiles q = 0 and q = 1 of
- * bz_window_quantile).  mn, mx: uint8 H x W, row stride ld_out; exact.
+ * the paper's local extremes, which it keeps with deques).  Two separable
+ * passes through a 16-bit H x W field in `workspace` (DEVICE memory of at
+ * least bz_extremes_workspace_size(H, W) bytes, 4-byte aligned, overlapping
+ * no input or output).  mn, mx: uint8 H x W, row stride ld_out; exact.
  */
 bz_status bz_window_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
-                           uint8_t *mx, ptrdiff_t ld_out, bz_stream stream);
+                           uint8_t *mx, ptrdiff_t ld_out, void *workspace, size_t ws_bytes,
+                           bz_stream stream);
 
 /*
  * Bernsen's midrange rule (cited by the paper beside Table 1 as a method on
  * local extremes): with mn, mx the window minimum and maximum,
  * mask = 1 where mx - mn >= contrast_min (0 .. 256) and 2 I < mn + mx, else
  * 0 (windows of lower contrast are background).  mn and mx (row stride
- * ld_mm) are written as well; all integer, exact.
+ * ld_mm) are written as well; all integer, exact.  Workspace as for
+ * bz_window_minmax.
  */
 bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int contrast_min,
                      uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
-                     bz_stream stream);
+                     void *workspace, size_t ws_bytes, bz_stream stream);
 
 /* Thresholding rule of a batched item. */
 enum { BZ_METHOD_SAUVOLA = 1, BZ_METHOD_NIBLACK = 2 };

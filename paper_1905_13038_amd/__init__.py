@@ -54,10 +54,12 @@ lib.bz_niblack.restype = _I
 lib.bz_niblack.argtypes = [_P, _I, _I, _PD, _I, _I, _F, _P, _PD, _P, _P, _PD, _P]
 lib.bz_window_quantile.restype = _I
 lib.bz_window_quantile.argtypes = [_P, _I, _I, _PD, _I, _I, _D, _P, _PD, _P, _PD, _P]
+lib.bz_extremes_workspace_size.restype = _SZ
+lib.bz_extremes_workspace_size.argtypes = [_I, _I]
 lib.bz_window_minmax.restype = _I
-lib.bz_window_minmax.argtypes = [_P, _I, _I, _PD, _I, _I, _P, _P, _PD, _P]
+lib.bz_window_minmax.argtypes = [_P, _I, _I, _PD, _I, _I, _P, _P, _PD, _P, _SZ, _P]
 lib.bz_bernsen.restype = _I
-lib.bz_bernsen.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _P, _PD, _P]
+lib.bz_bernsen.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _P, _PD, _P, _SZ, _P]
 lib.bz_global_stats.restype = _I
 lib.bz_global_stats.argtypes = [_P, _I, _I, _PD, _P, _P]
 lib.bz_threshold.restype = _I
@@ -321,8 +323,10 @@ def window_minmax(img: torch.Tensor, h: int, w: int):
     img, H, W, ld = _image(img)
     mn = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     mx = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    nb = int(lib.bz_extremes_workspace_size(H, W))
+    ws = torch.empty(nb, dtype=torch.uint8, device=img.device)
     _check(lib.bz_window_minmax(img.data_ptr(), H, W, ld, h, w, mn.data_ptr(), mx.data_ptr(), W,
-                                _stream(img)), "bz_window_minmax")
+                                ws.data_ptr(), nb, _stream(img)), "bz_window_minmax")
     return mn, mx
 
 
@@ -333,8 +337,10 @@ def bernsen(img: torch.Tensor, h: int, w: int, contrast_min: int = 15):
     mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     mn = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     mx = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    nb = int(lib.bz_extremes_workspace_size(H, W))
+    ws = torch.empty(nb, dtype=torch.uint8, device=img.device)
     _check(lib.bz_bernsen(img.data_ptr(), H, W, ld, h, w, int(contrast_min), mask.data_ptr(), W,
-                          mn.data_ptr(), mx.data_ptr(), W, _stream(img)), "bz_bernsen")
+                          mn.data_ptr(), mx.data_ptr(), W, ws.data_ptr(), nb, _stream(img)), "bz_bernsen")
     return mask, mn, mx
 
 

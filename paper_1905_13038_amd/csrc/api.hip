@@ -361,27 +361,6 @@ bz_status bz_window_quantile(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
 }
 
 namespace {
-QuantJob quantile_job(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, double q, uint8_t *Q,
-                      ptrdiff_t ld_Q)
-{
-    QuantJob j;
-    memset(&j, 0, sizeof(j));
-    j.I = I;
-    j.ldI = ld_I;
-    j.H = H;
-    j.W = W;
-    j.h = h;
-    j.w = w;
-    j.o = (h + 1) / 2;
-    j.u = h / 2;
-    j.l = (w + 1) / 2;
-    j.r = w / 2;
-    j.q = q;
-    j.Q = Q;
-    j.ldQ = ld_Q;
-    return j;
-}
-
 // Validate the extremes outputs (and the mask, when given) of a min/max call.
 bz_status check_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
                        uint8_t *mx, ptrdiff_t ld_out, uint8_t *mask, ptrdiff_t ld_mask)
@@ -401,33 +380,45 @@ bz_status check_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, in
 }
 }  // namespace
 
-bz_status bz_window_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
-                           uint8_t *mx, ptrdiff_t ld_out, bz_stream stream)
+size_t bz_extremes_workspace_size(int H, int W)
 {
-    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_out, nullptr, 0);
+    if (H < 1 || W < 1) return 0;
+    return extremes_workspace_bytes(H, W);
+}
+
+namespace {
+bz_status extremes_call(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int cmin, uint8_t *mask,
+                        ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm, void *workspace,
+                        size_t ws_bytes, bz_stream stream)
+{
+    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_mm, mask, ld_mask);
     if (st != BZ_OK) return st;
+    if (workspace == nullptr || !aligned(workspace, 4)) return BZ_ERR_INVALID;
+    if (ws_bytes < extremes_workspace_bytes(H, W)) return BZ_ERR_WORKSPACE;
+    const Range ws{(uintptr_t)workspace, (uintptr_t)workspace + extremes_workspace_bytes(H, W)};
+    if (overlaps(ws, span(I, H, W, ld_I, 1)) || overlaps(ws, span(mn, H, W, ld_mm, 1)) ||
+        overlaps(ws, span(mx, H, W, ld_mm, 1)) || (mask && overlaps(ws, span(mask, H, W, ld_mask, 1))))
+        return BZ_ERR_ALIAS;
     if (inject_launch_fault()) return BZ_ERR_HIP;
-    hipError_t e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 0.0, mn, ld_out), (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 1.0, mx, ld_out), (hipStream_t)stream);
-    return hip_status(e);
+    return hip_status(launch_extremes(I, ld_I, H, W, h, w, (uint16_t *)workspace, mn, mx, ld_mm, cmin, mask,
+                                      mask ? ld_mask : 0, (hipStream_t)stream));
+}
+}  // namespace
+
+bz_status bz_window_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
+                           uint8_t *mx, ptrdiff_t ld_out, void *workspace, size_t ws_bytes, bz_stream stream)
+{
+    return extremes_call(I, H, W, ld_I, h, w, 0, nullptr, 0, mn, mx, ld_out, workspace, ws_bytes, stream);
 }
 
 bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int contrast_min,
                      uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
-                     bz_stream stream)
+                     void *workspace, size_t ws_bytes, bz_stream stream)
 {
     if (mask == nullptr) return BZ_ERR_INVALID;
     if (contrast_min < 0 || contrast_min > 256) return BZ_ERR_INVALID;
-    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_mm, mask, ld_mask);
-    if (st != BZ_OK) return st;
-    if (inject_launch_fault()) return BZ_ERR_HIP;
-    hipError_t e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 0.0, mn, ld_mm), (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = launch_quantile(quantile_job(I, H, W, ld_I, h, w, 1.0, mx, ld_mm), (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = launch_bernsen(I, ld_I, mn, mx, ld_mm, H, W, contrast_min, mask, ld_mask, (hipStream_t)stream);
-    return hip_status(e);
+    return extremes_call(I, H, W, ld_I, h, w, contrast_min, mask, ld_mask, mn, mx, ld_mm, workspace, ws_bytes,
+                         stream);
 }
 
 size_t bz_batched_workspace_size(int count)

@@ -103,10 +103,11 @@ int batch_grid(int variant);
 hipError_t launch_global_stats(const uint8_t *I, int H, int W, int64_t ld, GlobalStats *out,
                                hipStream_t stream);
 
-// Bernsen's decision over an image and its window extremes mn, mx (row
-// stride ldE each).
-hipError_t launch_bernsen(const uint8_t *I, int64_t ldI, const uint8_t *mn, const uint8_t *mx, int64_t ldE,
-                          int H, int W, int cmin, uint8_t *mask, int64_t ldM, hipStream_t stream);
+// Window extremes (two separable passes through a 16-bit H x W field V in
+// caller memory), and Bernsen's decision when mask is not null.
+size_t extremes_workspace_bytes(int H, int W);
+hipError_t launch_extremes(const uint8_t *I, int64_t ldI, int H, int W, int h, int w, uint16_t *V, uint8_t *mn,
+                           uint8_t *mx, int64_t ldE, int cmin, uint8_t *mask, int64_t ldM, hipStream_t stream);
 
 // Windowed quantile (Section 3.4).
 struct QuantJob {

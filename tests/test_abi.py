@@ -190,12 +190,20 @@ print(L.bz_global_stats(0x100000, 64, 64, 64, 0xC00000, None))
 
 def test_validation_minmax_and_bernsen(bz):
     L = bz.lib
-    MN, MX = 0xD00000, 0xE00000
-    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, MN, MN + 64, 64, None) == 3   # mn, mx overlap
-    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, IMG + 5, MX, 64, None) == 3
-    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 300, MN, MX, 64, None) == 2
-    assert L.bz_window_minmax(IMG, 64, 64, 64, 9, 9, None, MX, 64, None) == 1
-    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 15, None, 64, MN, MX, 64, None) == 1
-    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, -1, OUT, 64, MN, MX, 64, None) == 1
-    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 257, OUT, 64, MN, MX, 64, None) == 1
-    assert L.bz_bernsen(IMG, 64, 64, 64, 9, 9, 15, MN + 3, 64, MN, MX, 64, None) == 3
+    MN, MX, WS = 0xD00000, 0xE00000, 0xF00000
+    nb = L.bz_extremes_workspace_size(64, 64)
+    assert nb == 2 * 64 * 64
+    mm = lambda mn=MN, mx=MX, ws=WS, n=nb, w=9: L.bz_window_minmax(IMG, 64, 64, 64, 9, w, mn, mx, 64, ws, n, None)
+    assert mm(mx=MN + 64) == 3            # mn, mx overlap
+    assert mm(mn=IMG + 5) == 3            # output inside the input
+    assert mm(w=300) == 2
+    assert mm(mn=None) == 1
+    assert mm(ws=None) == 1
+    assert mm(ws=WS + 2) == 1             # workspace alignment
+    assert mm(n=nb - 1) == 4              # workspace too small
+    assert mm(ws=MN + 100) == 3           # workspace over an output
+    bs = lambda c=15, mask=OUT: L.bz_bernsen(IMG, 64, 64, 64, 9, 9, c, mask, 64, MN, MX, 64, WS, nb, None)
+    assert bs(mask=None) == 1
+    assert bs(c=-1) == 1
+    assert bs(c=257) == 1
+    assert bs(mask=MN + 3) == 3
