@@ -1,6 +1,6 @@
 // Window minimum and maximum over clipped windows, separably: a vertical pass
-// into a 16-bit field (low byte max, high byte min), then a horizontal pass
-// into the outputs (and, for Bernsen's rule, the mask).
+// into a 16-bit field (low byte max, high byte min) stored transposed, then a
+// horizontal pass into the outputs (and, for Bernsen's rule, the mask).
 //
 // Each pass splits its axis into strips of h (or w) outputs.  All windows of
 // a strip contain one pivot element c (for rows: c = y0 + u, since the
@@ -29,98 +29,117 @@ constexpr uint32_t EXT_NONE = 0xff00u;  // max 0, min 255
 // (one at a time left each lane waiting on the latency of every element).
 constexpr int EXT_BATCH = 8;
 
-// Vertical pass.  Workgroup (bx, sy): columns bx*64 .. +63 (one per lane),
-// output rows y0 = sy*h .. y0+h-1; writes V[y][x] (16 bits) for them.
-__global__ __launch_bounds__(EXT_LANES) void k_ext_v(const uint8_t *I, int64_t ld, int H, int W, int h, int o,
-                                                     int u, uint16_t *V)
+// LDS rows of 66 16-bit entries (33 dwords, an odd count): a wavefront that
+// reads entry (t, k) with t across its lanes then hits distinct banks.
+constexpr int EXT_PITCH = EXT_LANES + 2;
+
+// One lane's strip along its line of len elements (fetched by at(i); the
+// identity outside [0, len)): the window extremes of the n outputs a0 ..
+// a0+n-1, where the window of output a covers a-f+1 .. a+pv and n = f + pv,
+// so that every window of the strip holds the pivot a0 + pv.  The result for
+// output t goes to s[t * EXT_PITCH].
+template <typename F>
+__device__ __forceinline__ void ext_strip(F at, int len, int a0, int n, int f, int pv, uint16_t *s)
 {
-    extern __shared__ uint16_t suf[];  // [h][64]
-    const int x = blockIdx.x * EXT_LANES + threadIdx.x;
-    const int y0 = blockIdx.y * h;
-    const int c = y0 + u;  // pivot row
-    const bool col = x < W;
-    // suffix extremes of rows y0-o+1+j .. c, j = h-1 down to 0
+    // suffix extremes of elements a0-f+1+j .. a0+pv, j = n-1 down to 0
     uint32_t acc = EXT_NONE;
-    for (int jb = h - 1; jb >= 0; jb -= EXT_BATCH) {
+    for (int jb = n - 1; jb >= 0; jb -= EXT_BATCH) {
         uint32_t v[EXT_BATCH];
 #pragma unroll
         for (int q = 0; q < EXT_BATCH; ++q) {
-            const int r = y0 - o + 1 + jb - q;
-            v[q] = (col && jb - q >= 0 && r >= 0 && r < H) ? ext_pack(I[(int64_t)r * ld + x]) : EXT_NONE;
+            const int i = a0 - f + 1 + jb - q;
+            v[q] = (jb - q >= 0 && i >= 0 && i < len) ? at(i) : EXT_NONE;
         }
 #pragma unroll
         for (int q = 0; q < EXT_BATCH; ++q) {
             if (jb - q < 0) break;
             acc = ext_join(acc, v[q]);
-            suf[(jb - q) * EXT_LANES + threadIdx.x] = (uint16_t)acc;
+            s[(jb - q) * EXT_PITCH] = (uint16_t)acc;
         }
     }
-    // prefix extremes of rows c .. c+t; output row y0+t
+    // prefix extremes of elements a0+pv .. a0+pv+t; the result for output t
+    // replaces suffix entry t (read just before by the same lane)
     acc = EXT_NONE;
-    for (int tb = 0; tb < h; tb += EXT_BATCH) {
+    for (int tb = 0; tb < n; tb += EXT_BATCH) {
         uint32_t v[EXT_BATCH];
 #pragma unroll
         for (int q = 0; q < EXT_BATCH; ++q) {
-            const int r = c + tb + q;
-            v[q] = (col && tb + q < h && r < H) ? ext_pack(I[(int64_t)r * ld + x]) : EXT_NONE;
+            const int i = a0 + pv + tb + q;
+            v[q] = (tb + q < n && i < len) ? at(i) : EXT_NONE;
         }
 #pragma unroll
         for (int q = 0; q < EXT_BATCH; ++q) {
-            const int t = tb + q, y = y0 + t;
-            if (t >= h || y >= H) break;
+            const int tq = tb + q;
+            if (tq >= n) break;
             acc = ext_join(acc, v[q]);
-            if (col) V[(int64_t)y * W + x] = (uint16_t)ext_join(acc, suf[t * EXT_LANES + threadIdx.x]);
+            uint16_t *e = &s[tq * EXT_PITCH];
+            *e = (uint16_t)ext_join(acc, *e);
         }
     }
 }
 
-// Horizontal pass.  Workgroup (sx, by): rows by*64 .. +63 (one per lane),
-// output columns x0 = sx*w .. x0+w-1.  Writes mn, mx and, when mask is not
-// null, Bernsen's decision from I.
-__global__ __launch_bounds__(EXT_LANES) void k_ext_h(const uint16_t *V, int H, int W, int w, int l, int r,
-                                                     uint8_t *mn, uint8_t *mx, int64_t ldE, const uint8_t *I,
-                                                     int64_t ldI, int cmin, uint8_t *mask, int64_t ldM)
+// Vertical pass.  Workgroup (bx, by): columns bx*64 .. +63 (one per lane),
+// the S strips of h rows from Y0 = by*S*h.  Writes the field transposed,
+// VT[x][y] = VT[x*H + y] (16 bits), through LDS, so that a store instruction
+// covers consecutive y of a column and each column's segment spans S*h rows.
+__global__ __launch_bounds__(EXT_LANES) void k_ext_v(const uint8_t *I, int64_t ld, int H, int W, int h, int o,
+                                                     int u, int S, uint16_t *VT)
 {
-    extern __shared__ uint16_t suf[];  // [w][64]
-    const int y = blockIdx.y * EXT_LANES + threadIdx.x;
-    const int x0 = blockIdx.x * w;
-    const int c = x0 + r;  // pivot column
-    if (y >= H) return;    // no barriers below: lanes are independent
-    const uint16_t *row = V + (int64_t)y * W;
-    uint32_t acc = EXT_NONE;
-    for (int jb = w - 1; jb >= 0; jb -= EXT_BATCH) {
-        uint32_t v[EXT_BATCH];
-#pragma unroll
-        for (int q = 0; q < EXT_BATCH; ++q) {
-            const int x = x0 - l + 1 + jb - q;
-            v[q] = (jb - q >= 0 && x >= 0 && x < W) ? (uint32_t)row[x] : EXT_NONE;
-        }
-#pragma unroll
-        for (int q = 0; q < EXT_BATCH; ++q) {
-            if (jb - q < 0) break;
-            acc = ext_join(acc, v[q]);
-            suf[(jb - q) * EXT_LANES + threadIdx.x] = (uint16_t)acc;
-        }
+    extern __shared__ uint16_t suf[];  // [S*h][65]
+    const int lane = threadIdx.x;
+    const int x0 = blockIdx.x * EXT_LANES;
+    const int x = x0 + lane;
+    const int Y0 = blockIdx.y * S * h;
+    const int R = min(S * h, H - Y0);  // rows of this workgroup
+    if (x < W) {
+        const uint8_t *col = I + x;
+        auto at = [=](int i) { return ext_pack(col[(int64_t)i * ld]); };
+        for (int sy = 0; sy * h < R; ++sy)
+            ext_strip(at, H, Y0 + sy * h, h, o, u, &suf[sy * h * EXT_PITCH + lane]);
     }
-    acc = EXT_NONE;
-    for (int tb = 0; tb < w; tb += EXT_BATCH) {
-        uint32_t v[EXT_BATCH], iv[EXT_BATCH];
-#pragma unroll
-        for (int q = 0; q < EXT_BATCH; ++q) {
-            const int x = c + tb + q, xo = x0 + tb + q;
-            v[q] = (tb + q < w && x < W) ? (uint32_t)row[x] : EXT_NONE;
-            iv[q] = (mask && tb + q < w && xo < W) ? (uint32_t)I[(int64_t)y * ldI + xo] : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < EXT_BATCH; ++q) {
-            const int t = tb + q, xo = x0 + t;
-            if (t >= w || xo >= W) break;
-            acc = ext_join(acc, v[q]);
-            const uint32_t e = ext_join(acc, suf[t * EXT_LANES + threadIdx.x]);
-            const uint32_t hi = e & 0xffu, lo = e >> 8;
-            mx[(int64_t)y * ldE + xo] = (uint8_t)hi;
-            mn[(int64_t)y * ldE + xo] = (uint8_t)lo;
-            if (mask) mask[(int64_t)y * ldM + xo] = ((int)(hi - lo) >= cmin && 2 * iv[q] < lo + hi) ? 1 : 0;
+    __syncthreads();
+    const int C = min(EXT_LANES, W - x0);
+    uint16_t *base = VT + (int64_t)x0 * H + Y0;
+    for (int i = lane; i < R * C; i += EXT_LANES) {
+        const int k = i / R, t = i - k * R;
+        base[(int64_t)k * H + t] = suf[t * EXT_PITCH + k];
+    }
+}
+
+// Horizontal pass over VT.  Workgroup (bx, by): rows by*64 .. +63 (one per
+// lane), the S strips of w columns from X0 = bx*S*w; reads VT[x][y] with
+// consecutive y across the lanes.  The results go through LDS, and rows are
+// stored with the lanes across columns: mn, mx and, when mask is not null,
+// Bernsen's decision from I.
+__global__ __launch_bounds__(EXT_LANES) void k_ext_h(const uint16_t *VT, int H, int W, int w, int l, int r,
+                                                     int S, uint8_t *mn, uint8_t *mx, int64_t ldE,
+                                                     const uint8_t *I, int64_t ldI, int cmin, uint8_t *mask,
+                                                     int64_t ldM)
+{
+    extern __shared__ uint16_t suf[];  // [S*w][65]
+    const int lane = threadIdx.x;
+    const int y0 = blockIdx.y * EXT_LANES;
+    const int y = y0 + lane;
+    const int X0 = blockIdx.x * S * w;
+    const int C = min(S * w, W - X0);  // columns of this workgroup
+    if (y < H) {
+        const uint16_t *row = VT + y;
+        auto at = [=](int i) { return (uint32_t)row[(int64_t)i * H]; };
+        for (int sx = 0; sx * w < C; ++sx)
+            ext_strip(at, W, X0 + sx * w, w, l, r, &suf[sx * w * EXT_PITCH + lane]);
+    }
+    __syncthreads();
+    const int R = min(EXT_LANES, H - y0);
+    for (int i = lane; i < R * C; i += EXT_LANES) {
+        const int k = i / C, t = i - k * C;
+        const uint32_t e = suf[t * EXT_PITCH + k];
+        const uint32_t hi = e & 0xffu, lo = e >> 8;
+        const int64_t yk = y0 + k, xo = X0 + t;
+        mx[yk * ldE + xo] = (uint8_t)hi;
+        mn[yk * ldE + xo] = (uint8_t)lo;
+        if (mask) {
+            const uint32_t iv = I[yk * ldI + xo];
+            mask[yk * ldM + xo] = ((int)(hi - lo) >= cmin && 2 * iv < lo + hi) ? 1 : 0;
         }
     }
 }
@@ -129,18 +148,23 @@ __global__ __launch_bounds__(EXT_LANES) void k_ext_h(const uint16_t *V, int H, i
 
 size_t extremes_workspace_bytes(int H, int W) { return (size_t)H * (size_t)W * sizeof(uint16_t); }
 
+// Strips per workgroup: enough that a column segment of the transposed field
+// spans 64 rows (128 bytes) and a row segment of the outputs 64 columns.
+int ext_strips(int len) { return (EXT_LANES + len - 1) / len; }
+
 hipError_t launch_extremes(const uint8_t *I, int64_t ldI, int H, int W, int h, int w, uint16_t *V, uint8_t *mn,
                            uint8_t *mx, int64_t ldE, int cmin, uint8_t *mask, int64_t ldM, hipStream_t stream)
 {
     const int o = (h + 1) / 2, u = h / 2, l = (w + 1) / 2, r = w / 2;
-    const dim3 gv((W + EXT_LANES - 1) / EXT_LANES, (H + h - 1) / h);
-    hipLaunchKernelGGL(k_ext_v, gv, dim3(EXT_LANES), (size_t)h * EXT_LANES * sizeof(uint16_t), stream, I, ldI,
-                       H, W, h, o, u, V);
+    const int Sv = ext_strips(h), Sh = ext_strips(w);
+    const dim3 gv((W + EXT_LANES - 1) / EXT_LANES, (H + Sv * h - 1) / (Sv * h));
+    hipLaunchKernelGGL(k_ext_v, gv, dim3(EXT_LANES), (size_t)Sv * h * EXT_PITCH * sizeof(uint16_t), stream, I,
+                       ldI, H, W, h, o, u, Sv, V);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 gh((W + w - 1) / w, (H + EXT_LANES - 1) / EXT_LANES);
-    hipLaunchKernelGGL(k_ext_h, gh, dim3(EXT_LANES), (size_t)w * EXT_LANES * sizeof(uint16_t), stream, V, H, W,
-                       w, l, r, mn, mx, ldE, I, ldI, cmin, mask, ldM);
+    const dim3 gh((W + Sh * w - 1) / (Sh * w), (H + EXT_LANES - 1) / EXT_LANES);
+    hipLaunchKernelGGL(k_ext_h, gh, dim3(EXT_LANES), (size_t)Sh * w * EXT_PITCH * sizeof(uint16_t), stream, V, H,
+                       W, w, l, r, Sh, mn, mx, ldE, I, ldI, cmin, mask, ldM);
     return hipGetLastError();
 }
 
