@@ -176,7 +176,8 @@ def soft_workload(dev, B=32, Hs=1024, Ws=1024, win=32, tau=2.0):
 
 def extras(sets, host, args):
     """The other measured workloads: window sweep, Niblack, mask-only,
-    mean/std, cache-warm, ragged batch, soft fwd+bwd, quantiles."""
+    mean/std, cache-warm, ragged batch, soft fwd+bwd, quantiles, Table 1,
+    host-memory streaming."""
     import torch
     import paper_1905_13038_amd as bz
     from docgen import gen_document
@@ -343,6 +344,58 @@ def extras(sets, host, args):
                          "hbm_frac": round(10.0 * px / us / 1e3 / HBM_PEAK_GBS, 4)}
         return res
 
+    def streamed():
+        # the banded host-memory path: page-locked image in, mask out, the
+        # call synchronous (wall clock, median); 2 bytes per pixel cross PCIe
+        dev = sets[0][0].device
+
+        def wall(fn, n):
+            ts = []
+            for _ in range(n):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+            return float(np.median(ts)) * 1e6
+
+        res = {}
+        src = torch.empty((H, W), dtype=torch.uint8, pin_memory=True)
+        src.copy_(torch.from_numpy(host))
+        outp = torch.empty((H, W), dtype=torch.uint8, pin_memory=True)
+        # row bands of 384 rows; column bands of 512, 2048 and 4096 columns
+        # (the last is one band: a single 2-D copy each way)
+        for band, axis in ((384, "rows"), (512, "columns"), (2048, "columns"), (4096, "columns")):
+            page = lambda: bz.binarize_streamed(src, 75, 75, "sauvola", 0.5, 128.0, out=outp, band=band,
+                                                axis=axis)
+            page()
+            us = wall(page, 5)
+            res["page_%dx%d_w75_%s_band%d" % (W, H, axis, band)] = {
+                "us": round(us, 1), "Gpix_s": round(px / us / 1e3, 2), "pcie_GB_s": round(2.0 * px / us / 1e3, 1)}
+        d = torch.empty((H, W), dtype=torch.uint8, device=dev)
+
+        def h2d():
+            d.copy_(src, non_blocking=True)
+            torch.cuda.synchronize()
+
+        def d2h():
+            outp.copy_(d, non_blocking=True)
+            torch.cuda.synchronize()
+        res["copy_h2d_GB_s"] = round(px / wall(h2d, 5) / 1e3, 1)
+        res["copy_d2h_GB_s"] = round(px / wall(d2h, 5) / 1e3, 1)
+        # scans of 32 pages' size binarized in place, in row bands: tall and
+        # wide, of the default depth (slots of about 32 MiB) and of 512 rows
+        for (ty, tx, band) in ((8, 4, None), (8, 4, 512), (4, 8, None)):
+            Hb, Wb = ty * H, tx * W
+            big = torch.empty((Hb, Wb), dtype=torch.uint8, pin_memory=True)
+            big.copy_(torch.from_numpy(np.tile(host, (ty, tx))))
+            scan = lambda: bz.binarize_streamed(big, 75, 75, "sauvola", 0.5, 128.0, out=big, band=band)
+            scan()
+            us = wall(scan, 3)
+            res["scan_%dx%d_w75_in_place_band_%s" % (Wb, Hb, band or "default")] = {
+                "us": round(us, 1), "Gpix_s": round(Hb * Wb / us / 1e3, 2),
+                "pcie_GB_s": round(2.0 * Hb * Wb / us / 1e3, 1)}
+            del big
+        return res
+
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
     guarded("mean_std_w75", mean_std)
@@ -352,6 +405,7 @@ def extras(sets, host, args):
     guarded("soft_fwd_bwd_32x1024x1024_h32", soft)
     guarded("quantile_2048x1536", quantiles)
     guarded("table1_4096x3072_w75", table1)
+    guarded("streamed_host", streamed)
     return out
 
 

@@ -19,8 +19,9 @@
  * Memory.  Every pointer is DEVICE memory owned by the caller unless stated
  *   otherwise.  The library never allocates or frees device memory.  A call
  *   enqueues its kernels on `stream` and returns without synchronising; the
- *   one exception is the set-up call bz_batched_plan, which synchronises its
- *   stream once.  Outputs must not overlap the input or each other (Section
+ *   exceptions are the set-up call bz_batched_plan, which synchronises its
+ *   stream once, and bz_binarize_streamed, whose image and mask live in host
+ *   memory and which returns when the mask is complete.  Outputs must not overlap the input or each other (Section
  *   3.2's aliasing assumption); overlapping byte ranges are rejected with
  *   BZ_ERR_ALIAS.  32-bit outputs must be 4-byte aligned.
  * Stream.  `stream` is a hipStream_t (NULL = the null stream).
@@ -211,6 +212,48 @@ typedef struct {
     float k, R;
     int method; /* BZ_METHOD_SAUVOLA or BZ_METHOD_NIBLACK */
 } bz_item;
+
+/* Sweep axis of bz_binarize_streamed. */
+enum { BZ_AXIS_AUTO = 0, BZ_AXIS_ROWS = 1, BZ_AXIS_COLUMNS = 2 };
+
+/* Device workspace bytes of bz_binarize_streamed (four band slots); 0 for
+ * invalid arguments. */
+size_t bz_stream_workspace_size(int H, int W, int h, int w, int band, int axis);
+
+/*
+ * Sauvola or Niblack (method BZ_METHOD_SAUVOLA or BZ_METHOD_NIBLACK, k and R
+ * as for bz_sauvola / bz_niblack; R is ignored by Niblack) over an image in
+ * HOST memory that need not fit on the device.  The image streams through the
+ * device in bands of `band` lines, each computed with the window's halo
+ * (h - 1 rows or w - 1 columns); the mask equals that of bz_sauvola /
+ * bz_niblack on the whole image.
+ * axis: BZ_AXIS_ROWS sweeps down the rows (bands of whole rows, each host
+ * transfer a run of full rows); BZ_AXIS_COLUMNS sweeps across the columns
+ * (bands of H rows by `band` columns), so that the resident part spans H
+ * elements per line: with the axis of the smaller extent, min{H, W}, as in
+ * Section 3.3.  BZ_AXIS_AUTO takes rows unless h + 1 rows of a row band
+ * would span 2^31 bytes, then columns.  (Host-to-device copies of short
+ * column segments run far below the copy engines' rate for whole rows.)
+ * I and mask are HOST pointers, row strides ld_I and ld_mask in elements (no
+ * device limit applies to them); page-locked memory (hipHostMalloc) lets the
+ * copies run at full rate beside the kernels.  mask may be I itself with
+ * ld_mask == ld_I: in-place binarization (Section 3.2).  The halo lines a
+ * band shares with the previous band are kept on the device, so no gray
+ * level is read after its line was overwritten; any other overlap of I and
+ * mask is BZ_ERR_ALIAS.  workspace: DEVICE memory of at least
+ * bz_stream_workspace_size(H, W, h, w, band, axis) bytes, 256-byte aligned.
+ * Bands are double-buffered: host-to-device copies run on load_stream,
+ * kernels and device copies on stream, device-to-host copies on store_stream,
+ * so that loading one band, computing another and storing a third overlap
+ * (any of the three may be the same stream, which serialises them).  Unlike
+ * the device calls this call is SYNCHRONOUS: it returns once the whole mask
+ * is in host memory.  BZ_ERR_RANGE also when h + 1 rows of a band's device
+ * slot would span 2^31 bytes or more.
+ */
+bz_status bz_binarize_streamed(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int method,
+                               float k, float R, uint8_t *mask, ptrdiff_t ld_mask, int band, int axis,
+                               void *workspace, size_t ws_bytes, bz_stream stream,
+                               bz_stream load_stream, bz_stream store_stream);
 
 /* Workspace bytes that bz_sauvola_batched needs for `count` items. */
 size_t bz_batched_workspace_size(int count);

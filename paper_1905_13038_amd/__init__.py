@@ -22,7 +22,7 @@ __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
     "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola",
     "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "window_minmax", "bernsen",
-    "LIB_PATH",
+    "binarize_streamed", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbinarize.so")
@@ -74,6 +74,10 @@ class bz_item(ctypes.Structure):
                 ("k", _F), ("R", _F), ("method", _I)]
 
 
+lib.bz_stream_workspace_size.restype = _SZ
+lib.bz_stream_workspace_size.argtypes = [_I, _I, _I, _I, _I, _I]
+lib.bz_binarize_streamed.restype = _I
+lib.bz_binarize_streamed.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _F, _F, _P, _PD, _I, _I, _P, _SZ, _P, _P, _P]
 lib.bz_batched_workspace_size.restype = _SZ
 lib.bz_batched_workspace_size.argtypes = [_I]
 lib.bz_batched_plan.restype = _I
@@ -342,6 +346,65 @@ def bernsen(img: torch.Tensor, h: int, w: int, contrast_min: int = 15):
     _check(lib.bz_bernsen(img.data_ptr(), H, W, ld, h, w, int(contrast_min), mask.data_ptr(), W,
                           mn.data_ptr(), mx.data_ptr(), W, ws.data_ptr(), nb, _stream(img)), "bz_bernsen")
     return mask, mn, mx
+
+
+_STREAM_METHODS = {"sauvola": 1, "niblack": 2}
+_AXES = {"auto": 0, "rows": 1, "columns": 2}
+_copy_streams = {}
+
+
+def _host_image(img, name):
+    if not isinstance(img, torch.Tensor) or img.dim() != 2 or img.dtype != torch.uint8:
+        raise ValueError("%s: expected a 2-D uint8 tensor" % name)
+    if img.is_cuda:
+        raise ValueError("%s: expected a host (CPU) tensor" % name)
+    if img.stride(1) != 1:
+        raise ValueError("%s: expected unit column stride" % name)
+    H, W = img.shape
+    return max(img.stride(0) if H > 1 else W, W)
+
+
+def binarize_streamed(img: torch.Tensor, h: int, w: int, method: str = "sauvola", k: float = 0.5,
+                      R: float = 128.0, out: torch.Tensor = None, band: int = None, axis: str = "auto",
+                      device=None):
+    """Sauvola or Niblack over a HOST (CPU) uint8 image, streamed through the
+    device in bands of rows or columns (``axis``: "rows", "columns" or
+    "auto", which takes rows where they fit) with the window's halo; returns
+    when the mask is complete.  ``out``: the CPU uint8 tensor for the mask,
+    which may be ``img`` itself (in-place binarization); by default a new
+    tensor, page-locked when ``img`` is.  ``band``: lines per band (default:
+    device slots of about 32 MiB).  Returns the mask."""
+    if method not in _STREAM_METHODS:
+        raise ValueError("method must be 'sauvola' or 'niblack'")
+    if axis not in _AXES:
+        raise ValueError("axis must be 'auto', 'rows' or 'columns'")
+    ld = _host_image(img, "img")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, pin_memory=img.is_pinned())
+    if tuple(out.shape) != (H, W):
+        raise ValueError("out: expected shape %s" % ((H, W),))
+    ld_out = _host_image(out, "out")
+    if band is None:
+        rows = axis == "rows" or (axis == "auto" and (h + 1) * (-(-W // 64) * 64) < (1 << 31))
+        cross, win = (W, h) if rows else (H, w)
+        band = max(1, max(64, (1 << 25) // max(cross, 1)) - (win - 1))
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    nb = int(lib.bz_stream_workspace_size(H, W, h, w, int(band), _AXES[axis]))
+    if nb == 0:
+        _check(BZ_ERR_INVALID, "bz_stream_workspace_size")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    if dev not in _copy_streams:  # default priority, one pair per device
+        _copy_streams[dev] = (torch.cuda.Stream(dev), torch.cuda.Stream(dev))
+    load, store = _copy_streams[dev]
+    with torch.cuda.device(dev):
+        cs = torch.cuda.current_stream(dev).cuda_stream
+        _check(lib.bz_binarize_streamed(img.data_ptr(), H, W, ld, h, w, _STREAM_METHODS[method], k, R,
+                                        out.data_ptr(), ld_out, int(band), _AXES[axis], ws.data_ptr(), nb,
+                                        ctypes.c_void_p(cs), ctypes.c_void_p(load.cuda_stream),
+                                        ctypes.c_void_p(store.cuda_stream)),
+               "bz_binarize_streamed")
+    return out
 
 
 # The other rules of Table 1: C-ABI code and parameter names, in order.

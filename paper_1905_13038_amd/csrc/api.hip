@@ -194,6 +194,91 @@ int default_batch_strip(int h)
     return s;
 }
 
+// Banded binarization of an image in host memory (Section 3.3: the sweep can
+// run along either axis, so the resident state can span min{H, W}; Section
+// 3.2: in-place binarization keeps the window's rows above the current ones
+// aside).  The image is cut into bands of `band` lines (rows or columns); band j's
+// outputs are lines Y .. Y+B-1 and its input lines A .. E-1 with the halo
+// A = Y - (before), E = Y + B + (after), clipped.  Inside the halo every window
+// of the band is the window of the whole image, clipped where the image ends,
+// so the band computed as an image of its own gives the whole image's results
+// on its output lines.  Two input and two output slots alternate; the halo
+// lines a band shares with the previous one come from that band's slot
+// (device to device), so each host line is read once, before the lines above
+// it are written back.
+struct BandGeom {
+    bool rows;             // bands of rows or of columns
+    int len, cross;        // extent along the sweep axis and across it
+    int before, after;     // window lines before and after its centre, along the sweep
+    int band;              // output lines per band
+    int64_t pitch;         // row stride of a device slot, bytes
+    int slot_rows;         // rows of a device slot
+    size_t slot_bytes;     // bytes of a slot, a multiple of 256
+};
+
+int64_t round_up64(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Slot rows of a band of rows at pitch round_up(W, 64) must keep h + 1 of
+// them below 2^31 bytes (the device calls' window span).
+bool rows_fit(int W, int h) { return (int64_t)(h + 1) * round_up64(W, 64) < ((int64_t)1 << 31); }
+
+BandGeom band_geom(int H, int W, int h, int w, int band, int axis)
+{
+    BandGeom g;
+    g.rows = axis == BZ_AXIS_ROWS || (axis == BZ_AXIS_AUTO && rows_fit(W, h));
+    g.len = g.rows ? H : W;
+    g.cross = g.rows ? W : H;
+    const int win = g.rows ? h : w;
+    g.before = (win + 1) / 2 - 1;
+    g.after = win / 2;
+    g.band = band < g.len ? band : g.len;
+    const int64_t lines = std::min<int64_t>((int64_t)g.band + win - 1, g.len);
+    g.pitch = g.rows ? round_up64(W, 64) : round_up64(lines, 64);
+    g.slot_rows = g.rows ? (int)lines : H;
+    g.slot_bytes = (size_t)round_up64(g.pitch * g.slot_rows, 256);
+    return g;
+}
+
+// Address of line t of a band buffer: a row (rows) or a column.
+template <typename T>
+T *band_line(T *base, const BandGeom &g, int64_t t, int64_t ld)
+{
+    return base + (g.rows ? t * ld : t);
+}
+
+// Copy `count` lines of g.cross elements between two 2-D buffers.
+hipError_t copy_lines(const BandGeom &g, void *dst, int64_t dld, const void *src, int64_t sld, int count,
+                      hipMemcpyKind kind, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    if (g.rows) return hipMemcpy2DAsync(dst, (size_t)dld, src, (size_t)sld, (size_t)g.cross, (size_t)count, kind, s);
+    return hipMemcpy2DAsync(dst, (size_t)dld, src, (size_t)sld, (size_t)count, (size_t)g.cross, kind, s);
+}
+
+bz_status stream_check(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int method, float k,
+                       float R, const uint8_t *mask, ptrdiff_t ld_mask, int band, int axis)
+{
+    // host buffers: no device limit on their strides, only the size guard
+    if (I == nullptr || mask == nullptr) return BZ_ERR_INVALID;
+    if (H < 1 || W < 1 || h < 1 || w < 1 || band < 1) return BZ_ERR_INVALID;
+    if (axis != BZ_AXIS_AUTO && axis != BZ_AXIS_ROWS && axis != BZ_AXIS_COLUMNS) return BZ_ERR_INVALID;
+    if (ld_I < W || ld_mask < W) return BZ_ERR_INVALID;
+    if (h > MAX_WIN || w > MAX_WIN) return BZ_ERR_RANGE;
+    if ((int64_t)H * (int64_t)ld_I > ((int64_t)1 << 46) || (int64_t)H * (int64_t)ld_mask > ((int64_t)1 << 46))
+        return BZ_ERR_RANGE;
+    if (method != BZ_METHOD_SAUVOLA && method != BZ_METHOD_NIBLACK) return BZ_ERR_INVALID;
+    if (!isfinite(k)) return BZ_ERR_INVALID;
+    if (method == BZ_METHOD_SAUVOLA && (!(k >= 0.0f) || !isfinite(R) || !(R > 0.0f))) return BZ_ERR_INVALID;
+    // in place (the same buffer and stride) or disjoint
+    const bool same = (const void *)mask == (const void *)I && ld_mask == ld_I;
+    if (!same && overlaps(span(I, H, W, ld_I, 1), span(mask, H, W, ld_mask, 1))) return BZ_ERR_ALIAS;
+    // a band's slot, read as an image, must meet the device calls' limits
+    // (h rows of it below 2^31 bytes)
+    const BandGeom g = band_geom(H, W, h, w, band, axis);
+    if ((int64_t)(h + 1) * g.pitch >= ((int64_t)1 << 31)) return BZ_ERR_RANGE;
+    return BZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -560,4 +645,75 @@ bz_status bz_soft_sauvola_bwd(const float *I, const float *gy, int B, int H, int
                                       (hipStream_t)stream));
 }
 
+size_t bz_stream_workspace_size(int H, int W, int h, int w, int band, int axis)
+{
+    if (H < 1 || W < 1 || h < 1 || w < 1 || h > MAX_WIN || w > MAX_WIN || band < 1) return 0;
+    if (axis != BZ_AXIS_AUTO && axis != BZ_AXIS_ROWS && axis != BZ_AXIS_COLUMNS) return 0;
+    return 4 * band_geom(H, W, h, w, band, axis).slot_bytes;
+}
+
+bz_status bz_binarize_streamed(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int method,
+                               float k, float R, uint8_t *mask, ptrdiff_t ld_mask, int band, int axis,
+                               void *workspace, size_t ws_bytes, bz_stream stream, bz_stream load_stream,
+                               bz_stream store_stream)
+{
+    bz_status st = stream_check(I, H, W, ld_I, h, w, method, k, R, mask, ld_mask, band, axis);
+    if (st != BZ_OK) return st;
+    const BandGeom g = band_geom(H, W, h, w, band, axis);
+    if (workspace == nullptr || !aligned(workspace, 256)) return BZ_ERR_INVALID;
+    if (ws_bytes < 4 * g.slot_bytes) return BZ_ERR_WORKSPACE;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    const int mode = method == BZ_METHOD_SAUVOLA ? MODE_SAUVOLA : MODE_NIBLACK;
+    hipStream_t cs = (hipStream_t)stream, ls = (hipStream_t)load_stream, ss = (hipStream_t)store_stream;
+    uint8_t *slot[4];
+    for (int i = 0; i < 4; ++i) slot[i] = (uint8_t *)workspace + (size_t)i * g.slot_bytes;
+    // per slot: loaded (its input is in), freed (no longer read), computed
+    // (its output is in), stored (its output is no longer read)
+    hipEvent_t ev[4][2] = {};
+    hipEvent_t(&loaded)[2] = ev[0], (&freed)[2] = ev[1], (&computed)[2] = ev[2], (&stored)[2] = ev[3];
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 8 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i / 2][i % 2], hipEventDisableTiming);
+    const int nb = (g.len + g.band - 1) / g.band;
+    auto first = [&](int j) { return std::max(j * g.band - g.before, 0); };                 // A of band j
+    auto last = [&](int j) { return std::min(j * g.band + g.band + g.after, g.len); };      // E of band j
+    for (int j = 0; j < nb && e == hipSuccess && st == BZ_OK; ++j) {
+        const int Y = j * g.band, B = std::min(g.band, g.len - Y), s = j & 1;
+        const int A = first(j), E = last(j);
+        const int N0 = j == 0 ? A : last(j - 1);  // first line read from the host
+        uint8_t *in = slot[s], *out = slot[2 + s];
+        // load the new lines once band j-2's kernel and band j-1's carry have
+        // read slot s; the lines a band shares with band j-1 arrive by the carry
+        if (j >= 2) e = hipStreamWaitEvent(ls, freed[s], 0);
+        if (e == hipSuccess)
+            e = copy_lines(g, band_line(in, g, N0 - A, g.pitch), g.pitch, band_line(I, g, N0, ld_I), ld_I, E - N0,
+                           hipMemcpyHostToDevice, ls);
+        if (e == hipSuccess) e = hipEventRecord(loaded[s], ls);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, loaded[s], 0);
+        if (e == hipSuccess && j >= 2) e = hipStreamWaitEvent(cs, stored[s], 0);
+        if (e != hipSuccess) break;
+        BoxJob job;
+        const int Hb = g.rows ? E - A : H, Wb = g.rows ? W : E - A;
+        st = make_threshold_job(mode, in, Hb, Wb, g.pitch, h, w, k, R, out, g.pitch, nullptr, nullptr, 0, job);
+        if (st == BZ_OK) st = run_box(job, cs);
+        if (st != BZ_OK) break;
+        // the halo band j+1 shares with this band, into the other slot (its
+        // previous reader, band j-1's kernel, precedes on this stream)
+        if (j + 1 < nb)
+            e = copy_lines(g, slot[s ^ 1], g.pitch, band_line(in, g, first(j + 1) - A, g.pitch), g.pitch,
+                           E - first(j + 1), hipMemcpyDeviceToDevice, cs);
+        if (e == hipSuccess) e = hipEventRecord(freed[s], cs);
+        if (e == hipSuccess) e = hipEventRecord(computed[s], cs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ss, computed[s], 0);
+        if (e == hipSuccess)
+            e = copy_lines(g, band_line(mask, g, Y, ld_mask), ld_mask, band_line(out, g, Y - A, g.pitch), g.pitch, B,
+                           hipMemcpyDeviceToHost, ss);
+        if (e == hipSuccess) e = hipEventRecord(stored[s], ss);
+    }
+    // the call returns with the host outputs complete
+    const hipError_t e1 = hipStreamSynchronize(cs), e2 = hipStreamSynchronize(ls), e3 = hipStreamSynchronize(ss);
+    for (int i = 0; i < 8; ++i)
+        if (ev[i / 2][i % 2]) (void)hipEventDestroy(ev[i / 2][i % 2]);
+    if (st != BZ_OK) return st;
+    return (e != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) ? BZ_ERR_HIP : BZ_OK;
+}
 }  // extern "C"

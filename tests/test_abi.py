@@ -207,3 +207,70 @@ def test_validation_minmax_and_bernsen(bz):
     assert bs(c=-1) == 1
     assert bs(c=257) == 1
     assert bs(mask=MN + 3) == 3
+
+
+def test_validation_streamed(bz):
+    # host image and mask, device workspace: statuses before any HIP call
+    L = bz.lib
+    H_, W_, BAND = 64, 48, 16
+    nb = L.bz_stream_workspace_size(H_, W_, 9, 9, BAND, 0)
+    # rows: slots of BAND + h - 1 rows at a 64-byte pitch, 256-byte rounded
+    assert nb == 4 * (((BAND + 8) * 64 + 255) // 256 * 256)
+    # auto takes rows also for a wide image; columns on request: H rows at a
+    # pitch of BAND + w - 1 rounded up to 64
+    assert L.bz_stream_workspace_size(20, 300, 5, 9, 16, 0) == 4 * (20 * 320)
+    assert L.bz_stream_workspace_size(20, 300, 5, 9, 16, 2) == 4 * ((20 * 64 + 255) // 256 * 256)
+    assert L.bz_stream_workspace_size(0, 8, 3, 3, 4, 0) == 0
+    assert L.bz_stream_workspace_size(8, 8, 3, 3, 0, 0) == 0
+    assert L.bz_stream_workspace_size(8, 8, 3, 3, 4, 3) == 0
+    # rows of 2^28 bytes: h + 1 = 10 of them span more than 2^31 bytes, so
+    # auto sweeps columns
+    wide = 1 << 28
+    assert L.bz_stream_workspace_size(8, wide, 9, 9, 16, 0) == L.bz_stream_workspace_size(8, wide, 9, 9, 16, 2)
+    WS, HOUT = 0xF00000, 0x900000
+
+    def call(I=IMG, ld=W_, mask=HOUT, ldm=W_, h=9, w=9, method=1, k=0.5, R=128.0, band=BAND, axis=0, ws=WS,
+             n=nb):
+        return L.bz_binarize_streamed(I, H_, W_, ld, h, w, method, k, R, mask, ldm, band, axis, ws, n, None,
+                                      None, None)
+
+    assert call(I=None) == 1
+    assert call(mask=None) == 1
+    assert call(ld=W_ - 1) == 1
+    assert call(band=0) == 1
+    assert call(axis=-1) == 1
+    assert call(axis=3) == 1
+    assert call(method=3) == 1           # only Sauvola and Niblack stream
+    assert call(k=-0.1) == 1             # Sauvola needs k >= 0
+    assert call(R=0.0) == 1
+    assert call(h=258) == 2
+    assert call(mask=IMG + 7) == 3       # partial overlap
+    assert call(mask=IMG, ldm=W_ + 1) == 3   # the same buffer at another stride
+    assert call(ws=None) == 1
+    assert call(ws=WS + 64) == 1         # workspace alignment
+    assert call(n=nb - 1) == 4
+    # in place and Niblack with any k pass validation (launch fault injected)
+    code = (
+        "import paper_1905_13038_amd as b; L = b.lib;"
+        "n = L.bz_stream_workspace_size(64, 48, 9, 9, 16, 2);"
+        "print(L.bz_binarize_streamed(0x100000, 64, 48, 48, 9, 9, 1, 0.5, 128.0, 0x100000, 48, 16, 2,"
+        " 0xF00000, n, None, None, None));"
+        "print(L.bz_binarize_streamed(0x100000, 64, 48, 48, 9, 9, 2, -0.3, 0.0, 0x900000, 48, 16, 1,"
+        " 0xF00000, n, None, None, None))"
+    )
+    env = dict(os.environ, BZ_FAULT_INJECT="launch")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
+                         text=True, check=True)
+    assert out.stdout.split() == ["5", "5"]
+
+
+def test_streamed_binding_refuses_device_arguments(bz):
+    import torch
+    with pytest.raises(ValueError):
+        bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.int16), 3, 3)
+    with pytest.raises(ValueError):
+        bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.uint8), 3, 3, method="wolf")
+    with pytest.raises(ValueError):
+        bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.uint8)[:, ::2], 3, 3)
+    with pytest.raises(ValueError):
+        bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.uint8), 3, 3, axis="diagonal")
