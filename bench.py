@@ -188,7 +188,11 @@ def extras(sets, host, args):
     st = torch.cuda.current_stream().cuda_stream
     out = {}
 
+    only = set(args.extras_only.split(",")) if args.extras_only else None
+
     def guarded(name, fn):
+        if only is not None and name not in only:
+            return
         try:
             out[name] = fn()
         except Exception as e:  # report, do not abort the bench line
@@ -417,6 +421,8 @@ def main():
     ap.add_argument("--sets", type=int, default=8, help="rotated buffer sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extras-only", default=None,
+                    help="comma-separated names of the extras to run (default: all)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (window sweep, batch, soft, quantiles)")
     ap.add_argument("--pmc", action="store_true",
