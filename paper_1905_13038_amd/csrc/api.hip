@@ -276,6 +276,7 @@ bz_status stream_check(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, in
     // (h rows of it below 2^31 bytes)
     const BandGeom g = band_geom(H, W, h, w, band, axis);
     if ((int64_t)(h + 1) * g.pitch >= ((int64_t)1 << 31)) return BZ_ERR_RANGE;
+    if (g.slot_bytes > ((size_t)1 << 46)) return BZ_ERR_RANGE;
     return BZ_OK;
 }
 
@@ -673,11 +674,14 @@ bz_status bz_binarize_streamed(const uint8_t *I, int H, int W, ptrdiff_t ld_I, i
     hipEvent_t(&loaded)[2] = ev[0], (&freed)[2] = ev[1], (&computed)[2] = ev[2], (&stored)[2] = ev[3];
     hipError_t e = hipSuccess;
     for (int i = 0; i < 8 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i / 2][i % 2], hipEventDisableTiming);
-    const int nb = (g.len + g.band - 1) / g.band;
-    auto first = [&](int j) { return std::max(j * g.band - g.before, 0); };                 // A of band j
-    auto last = [&](int j) { return std::min(j * g.band + g.band + g.after, g.len); };      // E of band j
+    // band arithmetic in 64 bits: Y + B + after may pass 2^31 near the size limit
+    const int nb = (int)(((int64_t)g.len + g.band - 1) / g.band);
+    auto first = [&](int j) { return (int)std::max<int64_t>((int64_t)j * g.band - g.before, 0); };  // A of band j
+    auto last = [&](int j) {                                                                       // E of band j
+        return (int)std::min<int64_t>((int64_t)j * g.band + g.band + g.after, g.len);
+    };
     for (int j = 0; j < nb && e == hipSuccess && st == BZ_OK; ++j) {
-        const int Y = j * g.band, B = std::min(g.band, g.len - Y), s = j & 1;
+        const int Y = (int)((int64_t)j * g.band), B = std::min(g.band, g.len - Y), s = j & 1;
         const int A = first(j), E = last(j);
         const int N0 = j == 0 ? A : last(j - 1);  // first line read from the host
         uint8_t *in = slot[s], *out = slot[2 + s];
