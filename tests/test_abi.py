@@ -249,9 +249,11 @@ def test_validation_streamed(bz):
     assert call(ws=None) == 1
     assert call(ws=WS + 64) == 1         # workspace alignment
     assert call(n=nb - 1) == 4
-    # a band slot above 2^46 bytes (2^30 rows of 2^16 bytes, binarized in place)
-    big = 1 << 30
-    assert L.bz_binarize_streamed(IMG, big, 1 << 16, 1 << 16, 9, 9, 1, 0.5, 128.0, IMG, 1 << 16, big, 1, WS, nb,
+    # a band slot above 2^46 bytes while the host image is within them: rows
+    # of 65537 bytes take a 65600-byte pitch on the device (in place, one band)
+    Hb, Wb = 1073700000, 65537
+    assert Hb * Wb <= 1 << 46 < Hb * 65600
+    assert L.bz_binarize_streamed(IMG, Hb, Wb, Wb, 9, 9, 1, 0.5, 128.0, IMG, Wb, Hb, 1, WS, nb,
                                   None, None, None) == 2
     # in place and Niblack with any k pass validation (launch fault injected)
     code = (
