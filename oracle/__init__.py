@@ -11,7 +11,7 @@ decisions.  Function docstrings cite the paper passage each one follows.
 
 Parity status: every function here is pinned by the ``-m "not gpu"`` tests
 (brute force, integral images, closed forms, invariants, library order
-statistics, finite differences); none is "parity unpinned" except the choice
+statistics and correlations, finite differences); none is "parity unpinned" except the choice
 of quantile definition itself (the paper does not define one; the inverse
 empirical CDF is used).
 """
@@ -221,6 +221,43 @@ def bernsen(I, h: int, w: int, contrast_min: int):
     lo, hi = mn.astype(np.int32), mx.astype(np.int32)
     mask = ((hi - lo >= int(contrast_min)) & (2 * Ii < lo + hi)).astype(np.uint8)
     return mask, mn, mx
+
+
+# Haar-like features (the rectangle features of Viola and Jones, which the
+# paper names as a use of recursive window sums): the sign of each a x b cell
+# of the template, row by row
+HAAR_EDGE_H, HAAR_EDGE_V, HAAR_LINE_H, HAAR_LINE_V, HAAR_CHECKER = 1, 2, 3, 4, 5
+HAAR_SIGNS = {HAAR_EDGE_H: ((1, -1),), HAAR_EDGE_V: ((1,), (-1,)), HAAR_LINE_H: ((1, -1, 1),),
+              HAAR_LINE_V: ((1,), (-1,), (1,)), HAAR_CHECKER: ((1, -1), (-1, 1))}
+
+
+def haar(I, a: int, b: int, kind: int):
+    """Haar-like feature of one template at every anchor where it fits in the
+    image (Section 4 names these features as computable from window sums
+    without integral images): the template is a grid of a x b cells with
+    signs HAAR_SIGNS[kind]; F[i, j] = sum over cells (m, n) of sign(m, n)
+    times the sum of I over rows i + m a .. i + (m+1) a - 1 and columns
+    j + n b .. j + (n+1) b - 1.  F has H - kv a + 1 rows and W - kh b + 1
+    columns (kv x kh cells).  Each cell sum is taken from the int64 integral
+    image of Section 2 (Z[i, j] = sum of I over rows < i and columns < j; a
+    rectangle's sum is a signed sum of its four corners)."""
+    X = np.asarray(I).astype(np.int64)
+    H, W = X.shape
+    signs = HAAR_SIGNS[kind]
+    kv, kh = len(signs), len(signs[0])
+    Hf, Wf = H - kv * a + 1, W - kh * b + 1
+    if Hf < 1 or Wf < 1:
+        raise ValueError("the template does not fit in the image")
+    Z = np.zeros((H + 1, W + 1), np.int64)
+    Z[1:, 1:] = X.cumsum(0).cumsum(1)
+    F = np.zeros((Hf, Wf), np.int64)
+    for m in range(kv):
+        for n in range(kh):
+            r, c = m * a, n * b
+            cell = (Z[r + a:r + a + Hf, c + b:c + b + Wf] - Z[r:r + Hf, c + b:c + b + Wf]
+                    - Z[r + a:r + a + Hf, c:c + Wf] + Z[r:r + Hf, c:c + Wf])
+            F += signs[m][n] * cell
+    return F
 
 
 def global_stats(I):
