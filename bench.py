@@ -400,6 +400,28 @@ def extras(sets, host, args):
             del big
         return res
 
+    def haar():
+        # Haar-like features on the headline page: 12 x 12 cells, and 48 x 48;
+        # algorithmic bytes 1 (I) + 4 (F) per output position
+        res = {}
+        img = sets[0][0]
+        for (a, kind) in ((12, "edge_h"), (12, "checker"), (48, "line_v")):
+            code, (kv, kh) = bz.HAAR[kind]
+            Hf, Wf = H - kv * a + 1, W - kh * a + 1
+            F = torch.empty((Hf, Wf), dtype=torch.int32, device=img.device)
+            nb = int(lib.bz_haar_workspace_size(H, W, a))
+            ws = torch.empty(nb, dtype=torch.uint8, device=img.device)
+
+            def f(i, a=a, code=code, F=F, ws=ws, nb=nb, Wf=Wf):
+                rc = lib.bz_haar_features(sets[i % len(sets)][0].data_ptr(), H, W, W, a, a, code, F.data_ptr(), Wf,
+                                          ws.data_ptr(), nb, st)
+                if rc != 0:
+                    raise RuntimeError("status %d" % rc)
+            us = _loop_us(f, 20)
+            res["%s_a%d" % (kind, a)] = {"us": round(us, 1), "Gpix_s": round(Hf * Wf / us / 1e3, 1),
+                                         "hbm_frac": round(5.0 * Hf * Wf / us / 1e3 / HBM_PEAK_GBS, 4)}
+        return res
+
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
     guarded("mean_std_w75", mean_std)
@@ -409,6 +431,7 @@ def extras(sets, host, args):
     guarded("soft_fwd_bwd_32x1024x1024_h32", soft)
     guarded("quantile_2048x1536", quantiles)
     guarded("table1_4096x3072_w75", table1)
+    guarded("haar_4096x3072", haar)
     guarded("streamed_host", streamed)
     return out
 

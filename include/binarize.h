@@ -213,6 +213,37 @@ typedef struct {
     int method; /* BZ_METHOD_SAUVOLA or BZ_METHOD_NIBLACK */
 } bz_item;
 
+/* Haar-like feature templates: a grid of a x b cells, signs row by row. */
+enum {
+    BZ_HAAR_EDGE_H = 1, /* [+ -]          1 x 2 cells */
+    BZ_HAAR_EDGE_V = 2, /* [+ ; -]        2 x 1 */
+    BZ_HAAR_LINE_H = 3, /* [+ - +]        1 x 3 */
+    BZ_HAAR_LINE_V = 4, /* [+ ; - ; +]    3 x 1 */
+    BZ_HAAR_CHECKER = 5 /* [+ - ; - +]    2 x 2 */
+};
+
+/* Workspace bytes of bz_haar_features: H - a + 1 rows of W uint32 (row stride
+ * rounded up to 64); 0 for invalid sizes. */
+size_t bz_haar_workspace_size(int H, int W, int a);
+
+/*
+ * Haar-like features (the rectangle features of Viola and Jones, which
+ * Section 4 names as computable from recursive window sums instead of an
+ * integral image) of one template at every anchor where the whole template
+ * lies in the image: with kv x kh cells of a rows by b columns,
+ * F[i * ld_F + j] = sum over cells (m, n) of sign(m, n) times the sum of I
+ * over rows i + m a .. i + (m+1) a - 1 and columns j + n b .. j + (n+1) b - 1,
+ * for 0 <= i < H - kv a + 1 and 0 <= j < W - kh b + 1 (exact int32).  The
+ * cell sums come from sliding column sums of a rows (Section 3.1's
+ * recursion) and row prefixes of them.  1 <= a, b <= 257 (BZ_ERR_RANGE
+ * above); a template larger than the image is BZ_ERR_INVALID.  F: int32,
+ * 4-byte aligned, ld_F >= W - kh b + 1.  workspace: at least
+ * bz_haar_workspace_size(H, W, a) bytes, 256-byte aligned, overlapping
+ * neither I nor F.
+ */
+bz_status bz_haar_features(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int a, int b, int kind, int32_t *F,
+                           ptrdiff_t ld_F, void *workspace, size_t ws_bytes, bz_stream stream);
+
 /* Sweep axis of bz_binarize_streamed. */
 enum { BZ_AXIS_AUTO = 0, BZ_AXIS_ROWS = 1, BZ_AXIS_COLUMNS = 2 };
 

@@ -22,7 +22,7 @@ __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
     "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola",
     "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "window_minmax", "bernsen",
-    "binarize_streamed", "LIB_PATH",
+    "binarize_streamed", "haar_features", "HAAR", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbinarize.so")
@@ -78,6 +78,10 @@ lib.bz_stream_workspace_size.restype = _SZ
 lib.bz_stream_workspace_size.argtypes = [_I, _I, _I, _I, _I, _I]
 lib.bz_binarize_streamed.restype = _I
 lib.bz_binarize_streamed.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _F, _F, _P, _PD, _I, _I, _P, _SZ, _P, _P, _P]
+lib.bz_haar_workspace_size.restype = _SZ
+lib.bz_haar_workspace_size.argtypes = [_I, _I, _I]
+lib.bz_haar_features.restype = _I
+lib.bz_haar_features.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _SZ, _P]
 lib.bz_batched_workspace_size.restype = _SZ
 lib.bz_batched_workspace_size.argtypes = [_I]
 lib.bz_batched_plan.restype = _I
@@ -346,6 +350,30 @@ def bernsen(img: torch.Tensor, h: int, w: int, contrast_min: int = 15):
     _check(lib.bz_bernsen(img.data_ptr(), H, W, ld, h, w, int(contrast_min), mask.data_ptr(), W,
                           mn.data_ptr(), mx.data_ptr(), W, ws.data_ptr(), nb, _stream(img)), "bz_bernsen")
     return mask, mn, mx
+
+
+# Haar-like feature templates: C-ABI code and cell grid (rows, columns)
+HAAR = {"edge_h": (1, (1, 2)), "edge_v": (2, (2, 1)), "line_h": (3, (1, 3)), "line_v": (4, (3, 1)),
+        "checker": (5, (2, 2))}
+
+
+def haar_features(img: torch.Tensor, a: int, b: int, kind: str) -> torch.Tensor:
+    """Haar-like feature ``kind`` (a key of HAAR) with cells of a rows by b
+    columns at every anchor where the template fits: an int32 tensor of
+    (H - kv a + 1) x (W - kh b + 1)."""
+    if kind not in HAAR:
+        raise ValueError("kind must be one of %s" % sorted(HAAR))
+    img, H, W, ld = _image(img)
+    code, (kv, kh) = HAAR[kind]
+    Hf, Wf = H - kv * a + 1, W - kh * b + 1
+    if Hf < 1 or Wf < 1:
+        raise ValueError("the template does not fit in the image")
+    F = torch.empty((Hf, Wf), dtype=torch.int32, device=img.device)
+    nb = int(lib.bz_haar_workspace_size(H, W, a))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=img.device)
+    _check(lib.bz_haar_features(img.data_ptr(), H, W, ld, a, b, code, F.data_ptr(), Wf, ws.data_ptr(), nb,
+                                _stream(img)), "bz_haar_features")
+    return F
 
 
 _STREAM_METHODS = {"sauvola": 1, "niblack": 2}

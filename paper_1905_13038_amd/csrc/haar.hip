@@ -1,0 +1,137 @@
+// Haar-like features (the rectangle features of Viola and Jones) of one
+// template at every anchor where it fits, from sliding rectangle sums rather
+// than an integral image (Section 4 names these features among the uses of
+// recursive window sums).  The template is a kv x kh grid of a x b cells with
+// signs; F[i][j] = sum of sign(m, n) * (sum of I over the cell anchored at
+// (i + m a, j + n b)).
+//
+// Three launches over a caller workspace V of Hv = H - a + 1 rows:
+//   k_haar_v       V[i][x] = sum of I over rows i .. i+a-1 of column x, slid
+//                  down a strip: add the entering row, subtract the leaving
+//                  one (the column recursion of Section 3.1);
+//   k_haar_prefix  each row of V becomes its inclusive prefix along x (in
+//                  place, wrap-around uint32);
+//   k_haar_combine a cell's sum is a difference of two prefix entries,
+//                  P_r[c + b - 1] - P_r[c - 1] (P_r[-1] = 0); F sums kv * kh
+//                  of them.
+// Every cell sum is below 2^32 (255 * 257 * 257), so the wrap-around
+// differences are exact, and |F| <= 2 * 255 * 257 * 257 < 2^31.
+#include "haar.hpp"
+
+namespace bz {
+namespace {
+
+constexpr int HAAR_THREADS = HAAR_BLOCK;
+constexpr int HAAR_STRIP = HAAR_ROWS;
+
+// Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
+                                                         int Hv, int S, int nbx, uint32_t *__restrict__ V,
+                                                         int64_t ldV)
+{
+    const int bx = blockIdx.x % nbx, sy = blockIdx.x / nbx;
+    const int x = bx * HAAR_THREADS + threadIdx.x;
+    const int y0 = sy * S;
+    if (x >= W) return;
+    const int y1 = min(y0 + S, Hv);
+    const uint8_t *col = I + x;
+    uint32_t c = 0;
+#pragma unroll 8
+    for (int r = 0; r < a; ++r) c += col[(int64_t)(y0 + r) * ld];  // y0 + a - 1 <= Hv - 1 + a - 1 = H - 1
+    V[(int64_t)y0 * ldV + x] = c;
+#pragma unroll 8
+    for (int y = y0 + 1; y < y1; ++y) {
+        c += (uint32_t)col[(int64_t)(y + a - 1) * ld] - (uint32_t)col[(int64_t)(y - 1) * ld];
+        V[(int64_t)y * ldV + x] = c;
+    }
+}
+
+// Workgroup r: row r of V, in chunks of 4 * 256 elements: a per-thread
+// prefix of four, a wavefront scan of the thread totals, the wavefront
+// totals through LDS, and the running total of the earlier chunks.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(uint32_t *__restrict__ V, int64_t ldV, int W)
+{
+    __shared__ uint32_t wsum[HAAR_THREADS / 64];
+    uint32_t *row = V + (int64_t)blockIdx.x * ldV;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < W; base += 4 * HAAR_THREADS) {
+        const int j = base + 4 * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = j + q < W ? row[j + q] : 0u;
+        v[1] += v[0];
+        v[2] += v[1];
+        v[3] += v[2];
+        uint32_t s = v[3];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)s, d, 64);
+            if (lane >= d) s += t;
+        }
+        if (lane == 63) wsum[wave] = s;
+        __syncthreads();
+        uint32_t before = carry, total = 0;
+#pragma unroll
+        for (int k = 0; k < HAAR_THREADS / 64; ++k) {
+            if (k < wave) before += wsum[k];
+            total += wsum[k];
+        }
+        __syncthreads();  // wsum is rewritten by the next chunk
+        const uint32_t excl = before + s - v[3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (j + q < W) row[j + q] = v[q] + excl;
+        carry += total;
+    }
+}
+
+// Workgroup (cx, i): outputs F[i][cx*256 .. +255].  neg: bit m * kh + n set
+// where cell (m, n) is negative.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *__restrict__ P, int64_t ldP, int a,
+                                                               int b, int kv, int kh, uint32_t neg, int Wf, int ncx,
+                                                               int32_t *__restrict__ F, int64_t ldF)
+{
+    const int cx = blockIdx.x % ncx, i = blockIdx.x / ncx;
+    const int j = cx * HAAR_THREADS + threadIdx.x;
+    if (j >= Wf) return;
+    uint32_t f = 0;
+    for (int m = 0; m < kv; ++m) {
+        const uint32_t *row = P + (int64_t)(i + m * a) * ldP;
+        uint32_t prev = j > 0 ? row[j - 1] : 0u;
+        for (int n = 0; n < kh; ++n) {
+            const uint32_t cur = row[j + (n + 1) * b - 1];  // <= Wf - 1 + kh b - 1 = W - 1
+            const uint32_t cell = cur - prev;
+            f += ((neg >> (m * kh + n)) & 1u) ? 0u - cell : cell;
+            prev = cur;
+        }
+    }
+    F[(int64_t)i * ldF + j] = (int32_t)f;
+}
+
+}  // namespace
+
+int64_t haar_ld(int W) { return ((int64_t)W + 63) / 64 * 64; }
+
+size_t haar_workspace_bytes(int H, int W, int a) { return (size_t)(H - a + 1) * (size_t)haar_ld(W) * 4; }
+
+hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b, int kv, int kh, uint32_t neg,
+                       uint32_t *V, int32_t *F, int64_t ldF, hipStream_t stream)
+{
+    const int Hv = H - a + 1, Hf = H - kv * a + 1, Wf = W - kh * b + 1;
+    const int64_t ldV = haar_ld(W);
+    const int nbx = (W + HAAR_THREADS - 1) / HAAR_THREADS;
+    const int nsy = (Hv + HAAR_STRIP - 1) / HAAR_STRIP;
+    hipLaunchKernelGGL(k_haar_v, dim3(nbx * nsy), dim3(HAAR_THREADS), 0, stream, I, ldI, W, a, Hv, HAAR_STRIP, nbx,
+                       V, ldV);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_haar_prefix, dim3(Hv), dim3(HAAR_THREADS), 0, stream, V, ldV, W);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int ncx = (Wf + HAAR_THREADS - 1) / HAAR_THREADS;
+    hipLaunchKernelGGL(k_haar_combine, dim3(ncx * Hf), dim3(HAAR_THREADS), 0, stream, V, ldV, a, b, kv, kh, neg, Wf,
+                       ncx, F, ldF);
+    return hipGetLastError();
+}
+
+}  // namespace bz

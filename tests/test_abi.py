@@ -280,3 +280,40 @@ def test_streamed_binding_refuses_device_arguments(bz):
         bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.uint8)[:, ::2], 3, 3)
     with pytest.raises(ValueError):
         bz.binarize_streamed(torch.zeros((8, 8), dtype=torch.uint8), 3, 3, axis="diagonal")
+
+
+def test_validation_haar(bz):
+    L = bz.lib
+    F, WS = 0xD00000, 0xF00000
+    nb = L.bz_haar_workspace_size(64, 48, 5)
+    assert nb == (64 - 5 + 1) * 64 * 4
+    assert L.bz_haar_workspace_size(4, 48, 5) == 0
+
+    def call(I=IMG, H=64, W=48, ld=48, a=5, b=6, kind=1, out=F, ldF=48, ws=WS, n=nb):
+        return L.bz_haar_features(I, H, W, ld, a, b, kind, out, ldF, ws, n, None)
+
+    assert call(I=None) == 1
+    assert call(out=None) == 1
+    assert call(kind=0) == 1
+    assert call(kind=6) == 1
+    assert call(ld=47) == 1
+    assert call(a=0) == 1
+    assert call(a=258) == 2
+    assert call(b=25) == 1            # two cells of 25 columns exceed W = 48
+    assert call(kind=4, a=22) == 1    # three cells of 22 rows exceed H = 64
+    assert call(ldF=36) == 1          # ld_F below the W - 2 b + 1 = 37 outputs per row
+    assert call(out=F + 2) == 1       # int32 output alignment
+    assert call(out=IMG + 64) == 3    # output over the input
+    assert call(ws=None) == 1
+    assert call(ws=WS + 4) == 1       # workspace alignment
+    assert call(n=nb - 1) == 4
+    assert call(ws=F + 256) == 3      # workspace over the output
+    code = (
+        "import paper_1905_13038_amd as b; L = b.lib;"
+        "print(L.bz_haar_features(0x100000, 64, 48, 48, 5, 6, 5, 0xD00000, 48, 0xF00000,"
+        " L.bz_haar_workspace_size(64, 48, 5), None))"
+    )
+    env = dict(os.environ, BZ_FAULT_INJECT="launch")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
+                         text=True, check=True)
+    assert out.stdout.strip() == "5"

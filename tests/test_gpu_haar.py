@@ -1,0 +1,71 @@
+"""GPU parity of the Haar-like features (bz_haar_features) against the
+oracle: exact int32 values for every template, small and ragged images, a
+strided input, 1 x 1 and 257-row cells, templates as large as the image, and
+the 3072 x 4096 page."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from docgen import gen_document
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"edge_h": oracle.HAAR_EDGE_H, "edge_v": oracle.HAAR_EDGE_V, "line_h": oracle.HAAR_LINE_H,
+         "line_v": oracle.HAAR_LINE_V, "checker": oracle.HAAR_CHECKER}
+
+
+@pytest.fixture(scope="module")
+def bz():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1905_13038_amd as pkg
+    return pkg
+
+
+def check(bz, I, a, b, kind, view=None):
+    print("haar", kind, I.shape, a, b, flush=True)
+    F = bz.haar_features(torch.from_numpy(np.ascontiguousarray(I)).cuda() if view is None else view, a, b, kind)
+    torch.cuda.synchronize()
+    ref = oracle.haar(I, a, b, KINDS[kind])
+    got = F.cpu().numpy().astype(np.int64)
+    assert got.shape == ref.shape and np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kind", sorted(KINDS))
+@pytest.mark.parametrize("H,W,a,b", [(120, 160, 6, 8), (203, 301, 5, 9), (31, 1100, 3, 257), (600, 45, 257, 7),
+                                     (17, 19, 1, 1)])
+def test_haar_matches_oracle(bz, kind, H, W, a, b):
+    kv, kh = bz.HAAR[kind][1]
+    if kv * a > H or kh * b > W:
+        pytest.skip("template larger than the image")
+    check(bz, gen_document(H, W, 500 + H, noise=10.0, stain=True), a, b, kind)
+
+
+@pytest.mark.parametrize("kind", sorted(KINDS))
+def test_haar_template_as_large_as_the_image(bz, kind):
+    kv, kh = bz.HAAR[kind][1]
+    a, b = 7, 5
+    check(bz, gen_document(kv * a, kh * b, 7, noise=10.0), a, b, kind)
+
+
+def test_haar_strided_input(bz):
+    I = gen_document(150, 277, 11, noise=10.0, stain=True)
+    big = torch.zeros((150, 290), dtype=torch.uint8, device="cuda")
+    big[:, 6:283] = torch.from_numpy(I).cuda()
+    for kind in sorted(KINDS):
+        check(bz, I, 9, 13, kind, view=big[:, 6:283])
+
+
+def test_haar_extremes_of_the_value_range(bz):
+    # all-255 cells against all-0 cells at the largest size: |F| = 255 * 257^2
+    a = b = 257
+    I = np.zeros((257, 514), np.uint8)
+    I[:, :257] = 255
+    check(bz, I, a, b, "edge_h")
+    check(bz, I[:, ::-1].copy(), a, b, "edge_h")
+
+
+@pytest.mark.parametrize("kind", ["edge_h", "checker", "line_v"])
+def test_haar_headline_page(bz, kind):
+    check(bz, gen_document(3072, 4096, 2, noise=10.0, stain=True), 12, 12, kind)
