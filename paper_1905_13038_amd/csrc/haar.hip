@@ -5,15 +5,16 @@
 // signs; F[i][j] = sum of sign(m, n) * (sum of I over the cell anchored at
 // (i + m a, j + n b)).
 //
-// Three launches over a caller workspace V of Hv = H - a + 1 rows:
+// Two or three launches over a caller workspace V of Hv = H - a + 1 rows:
 //   k_haar_v       V[i][x] = sum of I over rows i .. i+a-1 of column x, slid
 //                  down a strip: add the entering row, subtract the leaving
 //                  one (the column recursion of Section 3.1);
-//   k_haar_prefix  each row of V becomes its inclusive prefix along x (in
-//                  place, wrap-around uint32);
-//   k_haar_combine a cell's sum is a difference of two prefix entries,
-//                  P_r[c + b - 1] - P_r[c - 1] (P_r[-1] = 0); F sums kv * kh
-//                  of them.
+//   k_haar_row     per output row, the kv rows of V it needs become inclusive
+//                  prefixes along x in LDS (wrap-around uint32), and a cell's
+//                  sum is a difference of two prefix entries, P_r[c + b - 1] -
+//                  P_r[c - 1] (P_r[-1] = 0); F sums kv * kh of them;
+//   (rows of more than 32 KiB for the kv prefixes: k_haar_prefix turns V into
+//   its row prefixes in place, then k_haar_combine reads them.)
 // Every cell sum is below 2^32 (255 * 257 * 257), so the wrap-around
 // differences are exact, and |F| <= 2 * 255 * 257 * 257 < 2^31.
 #include "haar.hpp"
@@ -23,6 +24,9 @@ namespace {
 
 constexpr int HAAR_THREADS = HAAR_BLOCK;
 constexpr int HAAR_STRIP = HAAR_ROWS;
+// largest kv * W * 4 that k_haar_row keeps in LDS: five workgroups per CU
+// (with 48 KiB, three 4096-wide prefixes, the two-launch path measured faster)
+constexpr size_t HAAR_ROW_LDS = 32 * 1024;
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
@@ -46,20 +50,19 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restri
     }
 }
 
-// Workgroup r: row r of V, in chunks of 4 * 256 elements: a per-thread
-// prefix of four, a wavefront scan of the thread totals, the wavefront
-// totals through LDS, and the running total of the earlier chunks.
-__global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(uint32_t *__restrict__ V, int64_t ldV, int W)
+// Inclusive prefix of src[0 .. W) into dst (which may be src), by the whole
+// workgroup, in chunks of 4 * 256 elements: a per-thread prefix of four, a
+// wavefront scan of the thread totals, the wavefront totals through LDS, and
+// the running total of the earlier chunks.
+__device__ __forceinline__ void row_prefix(const uint32_t *src, uint32_t *dst, int W, uint32_t *wsum)
 {
-    __shared__ uint32_t wsum[HAAR_THREADS / 64];
-    uint32_t *row = V + (int64_t)blockIdx.x * ldV;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t carry = 0;
     for (int base = 0; base < W; base += 4 * HAAR_THREADS) {
         const int j = base + 4 * threadIdx.x;
         uint32_t v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = j + q < W ? row[j + q] : 0u;
+        for (int q = 0; q < 4; ++q) v[q] = j + q < W ? src[j + q] : 0u;
         v[1] += v[0];
         v[2] += v[1];
         v[3] += v[2];
@@ -81,23 +84,20 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(uint32_t *__restri
         const uint32_t excl = before + s - v[3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (j + q < W) row[j + q] = v[q] + excl;
+            if (j + q < W) dst[j + q] = v[q] + excl;
         carry += total;
     }
 }
 
-// Workgroup (cx, i): outputs F[i][cx*256 .. +255].  neg: bit m * kh + n set
-// where cell (m, n) is negative.
-__global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *__restrict__ P, int64_t ldP, int a,
-                                                               int b, int kv, int kh, uint32_t neg, int Wf, int ncx,
-                                                               int32_t *__restrict__ F, int64_t ldF)
+// One output position j: the kv x kh cells from the prefixes P_m (row m of
+// the template at P + m * step).  neg: bit m * kh + n set where cell (m, n)
+// is negative.
+__device__ __forceinline__ int32_t haar_at(const uint32_t *P, int64_t step, int j, int b, int kv, int kh,
+                                           uint32_t neg)
 {
-    const int cx = blockIdx.x % ncx, i = blockIdx.x / ncx;
-    const int j = cx * HAAR_THREADS + threadIdx.x;
-    if (j >= Wf) return;
     uint32_t f = 0;
     for (int m = 0; m < kv; ++m) {
-        const uint32_t *row = P + (int64_t)(i + m * a) * ldP;
+        const uint32_t *row = P + m * step;
         uint32_t prev = j > 0 ? row[j - 1] : 0u;
         for (int n = 0; n < kh; ++n) {
             const uint32_t cur = row[j + (n + 1) * b - 1];  // <= Wf - 1 + kh b - 1 = W - 1
@@ -106,7 +106,42 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *_
             prev = cur;
         }
     }
-    F[(int64_t)i * ldF + j] = (int32_t)f;
+    return (int32_t)f;
+}
+
+// Workgroup i: output row i.  Rows i, i + a, ... of V (one per row of the
+// template) are each read once, turned into prefixes in LDS, and the row's
+// features are combined from LDS.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_row(const uint32_t *__restrict__ V, int64_t ldV, int W,
+                                                           int a, int b, int kv, int kh, uint32_t neg, int Wf,
+                                                           int32_t *__restrict__ F, int64_t ldF)
+{
+    extern __shared__ uint32_t P[];  // [kv][W]
+    __shared__ uint32_t wsum[HAAR_THREADS / 64];
+    const int i = blockIdx.x;
+    for (int m = 0; m < kv; ++m) row_prefix(V + (int64_t)(i + m * a) * ldV, P + m * W, W, wsum);
+    __syncthreads();
+    for (int j = threadIdx.x; j < Wf; j += HAAR_THREADS) F[(int64_t)i * ldF + j] = haar_at(P, W, j, b, kv, kh, neg);
+}
+
+// Rows too wide for k_haar_row's LDS: every row of V becomes its prefix in
+// place (workgroup r: row r), then k_haar_combine reads the prefixes.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(uint32_t *__restrict__ V, int64_t ldV, int W)
+{
+    __shared__ uint32_t wsum[HAAR_THREADS / 64];
+    uint32_t *row = V + (int64_t)blockIdx.x * ldV;
+    row_prefix(row, row, W, wsum);
+}
+
+// Workgroup (cx, i): outputs F[i][cx*256 .. +255] from the prefixes in V.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *__restrict__ P, int64_t ldP, int a,
+                                                               int b, int kv, int kh, uint32_t neg, int Wf, int ncx,
+                                                               int32_t *__restrict__ F, int64_t ldF)
+{
+    const int cx = blockIdx.x % ncx, i = blockIdx.x / ncx;
+    const int j = cx * HAAR_THREADS + threadIdx.x;
+    if (j >= Wf) return;
+    F[(int64_t)i * ldF + j] = haar_at(P + (int64_t)i * ldP, (int64_t)a * ldP, j, b, kv, kh, neg);
 }
 
 }  // namespace
@@ -126,6 +161,12 @@ hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b
                        V, ldV);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const size_t lds = (size_t)kv * (size_t)W * sizeof(uint32_t);
+    if (lds <= HAAR_ROW_LDS) {
+        hipLaunchKernelGGL(k_haar_row, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kv, kh, neg, Wf,
+                           F, ldF);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_haar_prefix, dim3(Hv), dim3(HAAR_THREADS), 0, stream, V, ldV, W);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int ncx = (Wf + HAAR_THREADS - 1) / HAAR_THREADS;
