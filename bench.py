@@ -409,7 +409,7 @@ def extras(sets, host, args):
             code, (kv, kh) = bz.HAAR[kind]
             Hf, Wf = H - kv * a + 1, W - kh * a + 1
             F = torch.empty((Hf, Wf), dtype=torch.int32, device=img.device)
-            nb = int(lib.bz_haar_workspace_size(H, W, a))
+            nb = int(lib.bz_haar_workspace_size(H, W, a, code))
             ws = torch.empty(nb, dtype=torch.uint8, device=img.device)
 
             def f(i, a=a, code=code, F=F, ws=ws, nb=nb, Wf=Wf):

@@ -222,9 +222,11 @@ enum {
     BZ_HAAR_CHECKER = 5 /* [+ - ; - +]    2 x 2 */
 };
 
-/* Workspace bytes of bz_haar_features: H - a + 1 rows of W uint32 (row stride
- * rounded up to 64); 0 for invalid sizes. */
-size_t bz_haar_workspace_size(int H, int W, int a);
+/* Workspace bytes of bz_haar_features for template `kind`: H - a + 1 rows of
+ * W 16-bit column sums (row stride rounded up to 64; a column of at most 257
+ * gray levels sums below 2^16, Section 3.3), plus as many 32-bit row prefixes
+ * when kv * W > 8192 (kv: rows of cells); 0 for invalid arguments. */
+size_t bz_haar_workspace_size(int H, int W, int a, int kind);
 
 /*
  * Haar-like features (the rectangle features of Viola and Jones, which
@@ -238,7 +240,7 @@ size_t bz_haar_workspace_size(int H, int W, int a);
  * recursion) and row prefixes of them.  1 <= a, b <= 257 (BZ_ERR_RANGE
  * above); a template larger than the image is BZ_ERR_INVALID.  F: int32,
  * 4-byte aligned, ld_F >= W - kh b + 1.  workspace: at least
- * bz_haar_workspace_size(H, W, a) bytes, 256-byte aligned, overlapping
+ * bz_haar_workspace_size(H, W, a, kind) bytes, 256-byte aligned, overlapping
  * neither I nor F.
  */
 bz_status bz_haar_features(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int a, int b, int kind, int32_t *F,

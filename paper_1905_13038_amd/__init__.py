@@ -79,7 +79,7 @@ lib.bz_stream_workspace_size.argtypes = [_I, _I, _I, _I, _I, _I]
 lib.bz_binarize_streamed.restype = _I
 lib.bz_binarize_streamed.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _F, _F, _P, _PD, _I, _I, _P, _SZ, _P, _P, _P]
 lib.bz_haar_workspace_size.restype = _SZ
-lib.bz_haar_workspace_size.argtypes = [_I, _I, _I]
+lib.bz_haar_workspace_size.argtypes = [_I, _I, _I, _I]
 lib.bz_haar_features.restype = _I
 lib.bz_haar_features.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _SZ, _P]
 lib.bz_batched_workspace_size.restype = _SZ
@@ -369,7 +369,7 @@ def haar_features(img: torch.Tensor, a: int, b: int, kind: str) -> torch.Tensor:
     if Hf < 1 or Wf < 1:
         raise ValueError("the template does not fit in the image")
     F = torch.empty((Hf, Wf), dtype=torch.int32, device=img.device)
-    nb = int(lib.bz_haar_workspace_size(H, W, a))
+    nb = int(lib.bz_haar_workspace_size(H, W, a, code))
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=img.device)
     _check(lib.bz_haar_features(img.data_ptr(), H, W, ld, a, b, code, F.data_ptr(), Wf, ws.data_ptr(), nb,
                                 _stream(img)), "bz_haar_features")

@@ -721,10 +721,27 @@ bz_status bz_binarize_streamed(const uint8_t *I, int H, int W, ptrdiff_t ld_I, i
     if (st != BZ_OK) return st;
     return (e != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) ? BZ_ERR_HIP : BZ_OK;
 }
-size_t bz_haar_workspace_size(int H, int W, int a)
+namespace {
+// Cell grid and negative cells (bit m * kh + n) of a template; false if unknown.
+bool haar_template(int kind, int &kv, int &kh, uint32_t &neg)
 {
-    if (H < 1 || W < 1 || a < 1 || a > H) return 0;
-    return haar_workspace_bytes(H, W, a);
+    switch (kind) {
+    case BZ_HAAR_EDGE_H: kv = 1, kh = 2, neg = 2u; return true;
+    case BZ_HAAR_EDGE_V: kv = 2, kh = 1, neg = 2u; return true;
+    case BZ_HAAR_LINE_H: kv = 1, kh = 3, neg = 2u; return true;
+    case BZ_HAAR_LINE_V: kv = 3, kh = 1, neg = 2u; return true;
+    case BZ_HAAR_CHECKER: kv = 2, kh = 2, neg = 6u; return true;
+    default: return false;
+    }
+}
+}  // namespace
+
+size_t bz_haar_workspace_size(int H, int W, int a, int kind)
+{
+    int kv, kh;
+    uint32_t neg;
+    if (H < 1 || W < 1 || a < 1 || a > H || !haar_template(kind, kv, kh, neg)) return 0;
+    return haar_workspace_bytes(H, W, a, kv);
 }
 
 bz_status bz_haar_features(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int a, int b, int kind, int32_t *F,
@@ -735,14 +752,7 @@ bz_status bz_haar_features(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int a
     if (a > MAX_WIN || b > MAX_WIN) return BZ_ERR_RANGE;
     int kv, kh;
     uint32_t neg;  // bit m * kh + n: cell (m, n) negative
-    switch (kind) {
-    case BZ_HAAR_EDGE_H: kv = 1, kh = 2, neg = 2u; break;
-    case BZ_HAAR_EDGE_V: kv = 2, kh = 1, neg = 2u; break;
-    case BZ_HAAR_LINE_H: kv = 1, kh = 3, neg = 2u; break;
-    case BZ_HAAR_LINE_V: kv = 3, kh = 1, neg = 2u; break;
-    case BZ_HAAR_CHECKER: kv = 2, kh = 2, neg = 6u; break;
-    default: return BZ_ERR_INVALID;
-    }
+    if (!haar_template(kind, kv, kh, neg)) return BZ_ERR_INVALID;
     if ((int64_t)kv * a > H || (int64_t)kh * b > W) return BZ_ERR_INVALID;  // the template must fit
     const int Hf = H - kv * a + 1, Wf = W - kh * b + 1;
     bz_status st = check_out(F, Hf, Wf, ld_F, 4);
@@ -755,14 +765,13 @@ bz_status bz_haar_features(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int a
         ((int64_t)Wf + HAAR_BLOCK - 1) / HAAR_BLOCK * Hf * HAAR_BLOCK >= lim)
         return BZ_ERR_RANGE;
     if (workspace == nullptr || !aligned(workspace, 256)) return BZ_ERR_INVALID;
-    const size_t need = haar_workspace_bytes(H, W, a);
+    const size_t need = haar_workspace_bytes(H, W, a, kv);
     if (ws_bytes < need) return BZ_ERR_WORKSPACE;
     const Range in = span(I, H, W, ld_I, 1), out = span(F, Hf, Wf, ld_F, 4);
     const Range ws{(uintptr_t)workspace, (uintptr_t)workspace + need};
     if (overlaps(in, out) || overlaps(ws, in) || overlaps(ws, out)) return BZ_ERR_ALIAS;
     if (inject_launch_fault()) return BZ_ERR_HIP;
-    return hip_status(launch_haar(I, ld_I, H, W, a, b, kv, kh, neg, (uint32_t *)workspace, F, ld_F,
-                                  (hipStream_t)stream));
+    return hip_status(launch_haar(I, ld_I, H, W, a, b, kv, kh, neg, workspace, F, ld_F, (hipStream_t)stream));
 }
 
 }  // extern "C"

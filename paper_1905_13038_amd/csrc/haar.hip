@@ -8,13 +8,15 @@
 // Two or three launches over a caller workspace V of Hv = H - a + 1 rows:
 //   k_haar_v       V[i][x] = sum of I over rows i .. i+a-1 of column x, slid
 //                  down a strip: add the entering row, subtract the leaving
-//                  one (the column recursion of Section 3.1);
+//                  one (the column recursion of Section 3.1), stored in 16
+//                  bits (255 * 257 < 2^16, Section 3.3's bound);
 //   k_haar_row     per output row, the kv rows of V it needs become inclusive
 //                  prefixes along x in LDS (wrap-around uint32), and a cell's
 //                  sum is a difference of two prefix entries, P_r[c + b - 1] -
 //                  P_r[c - 1] (P_r[-1] = 0); F sums kv * kh of them;
-//   (rows of more than 32 KiB for the kv prefixes: k_haar_prefix turns V into
-//   its row prefixes in place, then k_haar_combine reads them.)
+//   (rows of more than 32 KiB for the kv prefixes: k_haar_prefix writes the
+//   row prefixes of V to a uint32 field P after V, then k_haar_combine reads
+//   them.)
 // Every cell sum is below 2^32 (255 * 257 * 257), so the wrap-around
 // differences are exact, and |F| <= 2 * 255 * 257 * 257 < 2^31.
 #include "haar.hpp"
@@ -30,7 +32,7 @@ constexpr size_t HAAR_ROW_LDS = 32 * 1024;
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
-                                                         int Hv, int S, int nbx, uint32_t *__restrict__ V,
+                                                         int Hv, int S, int nbx, uint16_t *__restrict__ V,
                                                          int64_t ldV)
 {
     const int bx = blockIdx.x % nbx, sy = blockIdx.x / nbx;
@@ -42,19 +44,19 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restri
     uint32_t c = 0;
 #pragma unroll 8
     for (int r = 0; r < a; ++r) c += col[(int64_t)(y0 + r) * ld];  // y0 + a - 1 <= Hv - 1 + a - 1 = H - 1
-    V[(int64_t)y0 * ldV + x] = c;
+    V[(int64_t)y0 * ldV + x] = (uint16_t)c;
 #pragma unroll 8
     for (int y = y0 + 1; y < y1; ++y) {
         c += (uint32_t)col[(int64_t)(y + a - 1) * ld] - (uint32_t)col[(int64_t)(y - 1) * ld];
-        V[(int64_t)y * ldV + x] = c;
+        V[(int64_t)y * ldV + x] = (uint16_t)c;
     }
 }
 
-// Inclusive prefix of src[0 .. W) into dst (which may be src), by the whole
+// Inclusive prefix of src[0 .. W) into dst, by the whole
 // workgroup, in chunks of 4 * 256 elements: a per-thread prefix of four, a
 // wavefront scan of the thread totals, the wavefront totals through LDS, and
 // the running total of the earlier chunks.
-__device__ __forceinline__ void row_prefix(const uint32_t *src, uint32_t *dst, int W, uint32_t *wsum)
+__device__ __forceinline__ void row_prefix(const uint16_t *src, uint32_t *dst, int W, uint32_t *wsum)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t carry = 0;
@@ -62,7 +64,7 @@ __device__ __forceinline__ void row_prefix(const uint32_t *src, uint32_t *dst, i
         const int j = base + 4 * threadIdx.x;
         uint32_t v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = j + q < W ? src[j + q] : 0u;
+        for (int q = 0; q < 4; ++q) v[q] = j + q < W ? (uint32_t)src[j + q] : 0u;
         v[1] += v[0];
         v[2] += v[1];
         v[3] += v[2];
@@ -112,7 +114,7 @@ __device__ __forceinline__ int32_t haar_at(const uint32_t *P, int64_t step, int 
 // Workgroup i: output row i.  Rows i, i + a, ... of V (one per row of the
 // template) are each read once, turned into prefixes in LDS, and the row's
 // features are combined from LDS.
-__global__ __launch_bounds__(HAAR_THREADS) void k_haar_row(const uint32_t *__restrict__ V, int64_t ldV, int W,
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_row(const uint16_t *__restrict__ V, int64_t ldV, int W,
                                                            int a, int b, int kv, int kh, uint32_t neg, int Wf,
                                                            int32_t *__restrict__ F, int64_t ldF)
 {
@@ -124,16 +126,16 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_row(const uint32_t *__res
     for (int j = threadIdx.x; j < Wf; j += HAAR_THREADS) F[(int64_t)i * ldF + j] = haar_at(P, W, j, b, kv, kh, neg);
 }
 
-// Rows too wide for k_haar_row's LDS: every row of V becomes its prefix in
-// place (workgroup r: row r), then k_haar_combine reads the prefixes.
-__global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(uint32_t *__restrict__ V, int64_t ldV, int W)
+// Rows too wide for k_haar_row's LDS: row r of P (uint32, same stride as V)
+// becomes the prefix of row r of V (workgroup r), then k_haar_combine reads P.
+__global__ __launch_bounds__(HAAR_THREADS) void k_haar_prefix(const uint16_t *__restrict__ V, uint32_t *__restrict__ P,
+                                                              int64_t ldV, int W)
 {
     __shared__ uint32_t wsum[HAAR_THREADS / 64];
-    uint32_t *row = V + (int64_t)blockIdx.x * ldV;
-    row_prefix(row, row, W, wsum);
+    row_prefix(V + (int64_t)blockIdx.x * ldV, P + (int64_t)blockIdx.x * ldV, W, wsum);
 }
 
-// Workgroup (cx, i): outputs F[i][cx*256 .. +255] from the prefixes in V.
+// Workgroup (cx, i): outputs F[i][cx*256 .. +255] from the prefixes in P.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *__restrict__ P, int64_t ldP, int a,
                                                                int b, int kv, int kh, uint32_t neg, int Wf, int ncx,
                                                                int32_t *__restrict__ F, int64_t ldF)
@@ -148,29 +150,43 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *_
 
 int64_t haar_ld(int W) { return ((int64_t)W + 63) / 64 * 64; }
 
-size_t haar_workspace_bytes(int H, int W, int a) { return (size_t)(H - a + 1) * (size_t)haar_ld(W) * 4; }
+bool haar_fused(int W, int kv) { return (size_t)kv * (size_t)W * sizeof(uint32_t) <= HAAR_ROW_LDS; }
+
+// V (uint16) first; for the two-launch path P (uint32) after it, 256-byte aligned.
+static size_t haar_v_bytes(int H, int W, int a)
+{
+    return ((size_t)(H - a + 1) * (size_t)haar_ld(W) * sizeof(uint16_t) + 255) / 256 * 256;
+}
+
+size_t haar_workspace_bytes(int H, int W, int a, int kv)
+{
+    const size_t v = haar_v_bytes(H, W, a);
+    return haar_fused(W, kv) ? v : v + (size_t)(H - a + 1) * (size_t)haar_ld(W) * sizeof(uint32_t);
+}
 
 hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b, int kv, int kh, uint32_t neg,
-                       uint32_t *V, int32_t *F, int64_t ldF, hipStream_t stream)
+                       void *ws, int32_t *F, int64_t ldF, hipStream_t stream)
 {
     const int Hv = H - a + 1, Hf = H - kv * a + 1, Wf = W - kh * b + 1;
     const int64_t ldV = haar_ld(W);
+    uint16_t *V = (uint16_t *)ws;
     const int nbx = (W + HAAR_THREADS - 1) / HAAR_THREADS;
     const int nsy = (Hv + HAAR_STRIP - 1) / HAAR_STRIP;
     hipLaunchKernelGGL(k_haar_v, dim3(nbx * nsy), dim3(HAAR_THREADS), 0, stream, I, ldI, W, a, Hv, HAAR_STRIP, nbx,
                        V, ldV);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)kv * (size_t)W * sizeof(uint32_t);
-    if (lds <= HAAR_ROW_LDS) {
+    if (haar_fused(W, kv)) {
+        const size_t lds = (size_t)kv * (size_t)W * sizeof(uint32_t);
         hipLaunchKernelGGL(k_haar_row, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kv, kh, neg, Wf,
                            F, ldF);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_haar_prefix, dim3(Hv), dim3(HAAR_THREADS), 0, stream, V, ldV, W);
+    uint32_t *P = (uint32_t *)((uint8_t *)ws + haar_v_bytes(H, W, a));
+    hipLaunchKernelGGL(k_haar_prefix, dim3(Hv), dim3(HAAR_THREADS), 0, stream, V, P, ldV, W);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int ncx = (Wf + HAAR_THREADS - 1) / HAAR_THREADS;
-    hipLaunchKernelGGL(k_haar_combine, dim3(ncx * Hf), dim3(HAAR_THREADS), 0, stream, V, ldV, a, b, kv, kh, neg, Wf,
+    hipLaunchKernelGGL(k_haar_combine, dim3(ncx * Hf), dim3(HAAR_THREADS), 0, stream, P, ldV, a, b, kv, kh, neg, Wf,
                        ncx, F, ldF);
     return hipGetLastError();
 }

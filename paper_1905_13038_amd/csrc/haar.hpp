@@ -10,13 +10,15 @@ namespace bz {
 constexpr int HAAR_BLOCK = 256;  // threads per workgroup of every Haar kernel
 constexpr int HAAR_ROWS = 64;    // rows of the vertical sums per workgroup
 
-// Row stride, in elements, of the vertical-sum workspace for W columns.
+// Row stride, in elements, of the vertical-sum field for W columns.
 int64_t haar_ld(int W);
-// Workspace bytes: H - a + 1 rows of haar_ld(W) uint32.
-size_t haar_workspace_bytes(int H, int W, int a);
+// Workspace bytes for a template of kv rows of cells: H - a + 1 rows of
+// haar_ld(W) uint16 column sums, and as many uint32 row prefixes when the kv
+// prefixes of a row do not fit the row kernel's LDS.
+size_t haar_workspace_bytes(int H, int W, int a, int kv);
 // Features of a kv x kh template of a x b cells (bit m * kh + n of neg set for
 // a negative cell) into F, (H - kv a + 1) x (W - kh b + 1) at row stride ldF.
 hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b, int kv, int kh, uint32_t neg,
-                       uint32_t *V, int32_t *F, int64_t ldF, hipStream_t stream);
+                       void *ws, int32_t *F, int64_t ldF, hipStream_t stream);
 
 }  // namespace bz

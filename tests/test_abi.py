@@ -285,9 +285,12 @@ def test_streamed_binding_refuses_device_arguments(bz):
 def test_validation_haar(bz):
     L = bz.lib
     F, WS = 0xD00000, 0xF00000
-    nb = L.bz_haar_workspace_size(64, 48, 5)
-    assert nb == (64 - 5 + 1) * 64 * 4
-    assert L.bz_haar_workspace_size(4, 48, 5) == 0
+    nb = L.bz_haar_workspace_size(64, 48, 5, 1)
+    assert nb == (64 - 5 + 1) * 64 * 2                  # 16-bit column sums only
+    # rows too wide for the row kernel (kv * W > 8192) add 32-bit prefixes
+    assert L.bz_haar_workspace_size(64, 9000, 5, 1) == ((60 * 9024 * 2 + 255) // 256 * 256) + 60 * 9024 * 4
+    assert L.bz_haar_workspace_size(4, 48, 5, 1) == 0
+    assert L.bz_haar_workspace_size(64, 48, 5, 9) == 0
 
     def call(I=IMG, H=64, W=48, ld=48, a=5, b=6, kind=1, out=F, ldF=48, ws=WS, n=nb):
         return L.bz_haar_features(I, H, W, ld, a, b, kind, out, ldF, ws, n, None)
@@ -311,7 +314,7 @@ def test_validation_haar(bz):
     code = (
         "import paper_1905_13038_amd as b; L = b.lib;"
         "print(L.bz_haar_features(0x100000, 64, 48, 48, 5, 6, 5, 0xD00000, 48, 0xF00000,"
-        " L.bz_haar_workspace_size(64, 48, 5), None))"
+        " L.bz_haar_workspace_size(64, 48, 5, 5), None))"
     )
     env = dict(os.environ, BZ_FAULT_INJECT="launch")
     out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
