@@ -230,7 +230,7 @@ size_t bz_haar_workspace_size(int H, int W, int a, int kind);
 
 /*
  * Haar-like features (the rectangle features of Viola and Jones, which
- * Section 4 names as computable from recursive window sums instead of an
+ * Section 3.4 names as computable from recursive window sums instead of an
  * integral image) of one template at every anchor where the whole template
  * lies in the image: with kv x kh cells of a rows by b columns,
  * F[i * ld_F + j] = sum over cells (m, n) of sign(m, n) times the sum of I

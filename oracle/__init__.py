@@ -233,7 +233,7 @@ HAAR_SIGNS = {HAAR_EDGE_H: ((1, -1),), HAAR_EDGE_V: ((1,), (-1,)), HAAR_LINE_H: 
 
 def haar(I, a: int, b: int, kind: int):
     """Haar-like feature of one template at every anchor where it fits in the
-    image (Section 4 names these features as computable from window sums
+    image (Section 3.4 names these features as computable from window sums
     without integral images): the template is a grid of a x b cells with
     signs HAAR_SIGNS[kind]; F[i, j] = sum over cells (m, n) of sign(m, n)
     times the sum of I over rows i + m a .. i + (m+1) a - 1 and columns

@@ -1,6 +1,6 @@
 // Haar-like features (the rectangle features of Viola and Jones) of one
 // template at every anchor where it fits, from sliding rectangle sums rather
-// than an integral image (Section 4 names these features among the uses of
+// than an integral image (Section 3.4 names these features among the uses of
 // recursive window sums).  The template is a kv x kh grid of a x b cells with
 // signs; F[i][j] = sum of sign(m, n) * (sum of I over the cell anchored at
 // (i + m a, j + n b)).
