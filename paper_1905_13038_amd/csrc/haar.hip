@@ -26,9 +26,11 @@ namespace {
 
 constexpr int HAAR_THREADS = HAAR_BLOCK;
 constexpr int HAAR_STRIP = HAAR_ROWS;
-// largest kv * W * 4 that k_haar_row keeps in LDS: five workgroups per CU
-// (with 48 KiB, three 4096-wide prefixes, the two-launch path measured faster)
-constexpr size_t HAAR_ROW_LDS = 32 * 1024;
+// largest kv * W that k_haar_row keeps in LDS (32 KiB of prefixes): five
+// workgroups per CU (with 48 KiB, three 4096-wide prefixes, the two-launch
+// path measured faster)
+constexpr int HAAR_ROW_ELEMS = 8192;
+constexpr size_t HAAR_ROW_LDS = HAAR_ROW_ELEMS * sizeof(uint32_t);
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
@@ -112,18 +114,72 @@ __device__ __forceinline__ int32_t haar_at(const uint32_t *P, int64_t step, int 
 }
 
 // Workgroup i: output row i.  Rows i, i + a, ... of V (one per row of the
-// template) are each read once, turned into prefixes in LDS, and the row's
-// features are combined from LDS.
+// template) are read whole into registers first (KV * W <= 8192, so at most
+// NCH chunks of 1024 per row, four elements per thread, one 8-byte load
+// each), then turned into prefixes in LDS chunk by chunk, and the row's
+// features are combined from LDS.  Reading V up to its padded row stride
+// stays inside the workspace; elements past W are taken as 0.
+template <int KV>
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_row(const uint16_t *__restrict__ V, int64_t ldV, int W,
-                                                           int a, int b, int kv, int kh, uint32_t neg, int Wf,
+                                                           int a, int b, int kh, uint32_t neg, int Wf,
                                                            int32_t *__restrict__ F, int64_t ldF)
 {
-    extern __shared__ uint32_t P[];  // [kv][W]
+    constexpr int CH = 4 * HAAR_THREADS;
+    constexpr int NCH = (HAAR_ROW_ELEMS / KV + CH - 1) / CH;
+    extern __shared__ uint32_t P[];  // [KV][W]
     __shared__ uint32_t wsum[HAAR_THREADS / 64];
     const int i = blockIdx.x;
-    for (int m = 0; m < kv; ++m) row_prefix(V + (int64_t)(i + m * a) * ldV, P + m * W, W, wsum);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t v[KV][NCH][4];
+#pragma unroll
+    for (int m = 0; m < KV; ++m) {
+        const uint16_t *row = V + (int64_t)(i + m * a) * ldV;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j = c * CH + 4 * threadIdx.x;
+            ushort4 e = make_ushort4(0, 0, 0, 0);
+            if (j < ldV) e = *(const ushort4 *)(row + j);  // ldV is a multiple of 64
+            v[m][c][0] = j < W ? e.x : 0u;
+            v[m][c][1] = j + 1 < W ? e.y : 0u;
+            v[m][c][2] = j + 2 < W ? e.z : 0u;
+            v[m][c][3] = j + 3 < W ? e.w : 0u;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < KV; ++m) {
+        uint32_t carry = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c * CH >= W) break;  // uniform
+            const int j = c * CH + 4 * threadIdx.x;
+            uint32_t *x = v[m][c];
+            x[1] += x[0];
+            x[2] += x[1];
+            x[3] += x[2];
+            uint32_t s = x[3];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t tt = (uint32_t)__shfl_up((int)s, d, 64);
+                if (lane >= d) s += tt;
+            }
+            if (lane == 63) wsum[wave] = s;
+            __syncthreads();
+            uint32_t before = carry, total = 0;
+#pragma unroll
+            for (int k = 0; k < HAAR_THREADS / 64; ++k) {
+                if (k < wave) before += wsum[k];
+                total += wsum[k];
+            }
+            __syncthreads();
+            const uint32_t excl = before + s - x[3];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j + q < W) P[m * W + j + q] = x[q] + excl;
+            carry += total;
+        }
+    }
     __syncthreads();
-    for (int j = threadIdx.x; j < Wf; j += HAAR_THREADS) F[(int64_t)i * ldF + j] = haar_at(P, W, j, b, kv, kh, neg);
+    for (int j = threadIdx.x; j < Wf; j += HAAR_THREADS) F[(int64_t)i * ldF + j] = haar_at(P, W, j, b, KV, kh, neg);
 }
 
 // Rows too wide for k_haar_row's LDS: row r of P (uint32, same stride as V)
@@ -178,8 +234,15 @@ hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b
     if (e != hipSuccess) return e;
     if (haar_fused(W, kv)) {
         const size_t lds = (size_t)kv * (size_t)W * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_haar_row, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kv, kh, neg, Wf,
-                           F, ldF);
+        if (kv == 1)
+            hipLaunchKernelGGL(k_haar_row<1>, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kh, neg,
+                               Wf, F, ldF);
+        else if (kv == 2)
+            hipLaunchKernelGGL(k_haar_row<2>, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kh, neg,
+                               Wf, F, ldF);
+        else
+            hipLaunchKernelGGL(k_haar_row<3>, dim3(Hf), dim3(HAAR_THREADS), lds, stream, V, ldV, W, a, b, kh, neg,
+                               Wf, F, ldF);
         return hipGetLastError();
     }
     uint32_t *P = (uint32_t *)((uint8_t *)ws + haar_v_bytes(H, W, a));
