@@ -8,7 +8,7 @@
 namespace bz {
 
 constexpr int HAAR_BLOCK = 256;  // threads per workgroup of every Haar kernel
-constexpr int HAAR_ROWS = 64;    // rows of the vertical sums per workgroup
+constexpr int HAAR_ROWS = 32;    // rows of the vertical sums per workgroup
 
 // Row stride, in elements, of the vertical-sum field for W columns.
 int64_t haar_ld(int W);
