@@ -225,7 +225,7 @@ enum {
 /* Workspace bytes of bz_haar_features for template `kind`: H - a + 1 rows of
  * W 16-bit column sums (row stride rounded up to 64; a column of at most 257
  * gray levels sums below 2^16, Section 3.3), plus as many 32-bit row prefixes
- * when kv * W > 8192 (kv: rows of cells); 0 for invalid arguments. */
+ * when kv * W > 12288 (kv: rows of cells); 0 for invalid arguments. */
 size_t bz_haar_workspace_size(int H, int W, int a, int kind);
 
 /*

@@ -14,7 +14,7 @@
 //                  prefixes along x in LDS (wrap-around uint32), and a cell's
 //                  sum is a difference of two prefix entries, P_r[c + b - 1] -
 //                  P_r[c - 1] (P_r[-1] = 0); F sums kv * kh of them;
-//   (rows of more than 32 KiB for the kv prefixes: k_haar_prefix writes the
+//   (rows of more than 48 KiB for the kv prefixes: k_haar_prefix writes the
 //   row prefixes of V to a uint32 field P after V, then k_haar_combine reads
 //   them.)
 // Every cell sum is below 2^32 (255 * 257 * 257), so the wrap-around
@@ -26,10 +26,10 @@ namespace {
 
 constexpr int HAAR_THREADS = HAAR_BLOCK;
 constexpr int HAAR_STRIP = HAAR_ROWS;
-// largest kv * W that k_haar_row keeps in LDS (32 KiB of prefixes): five
-// workgroups per CU (with 48 KiB, three 4096-wide prefixes, the two-launch
-// path measured faster)
-constexpr int HAAR_ROW_ELEMS = 8192;
+// largest kv * W that k_haar_row keeps in LDS: 48 KiB of prefixes, three
+// 4096-wide rows (measured faster than the two-launch path for them once each
+// row is loaded whole before its scan)
+constexpr int HAAR_ROW_ELEMS = 12288;
 constexpr size_t HAAR_ROW_LDS = HAAR_ROW_ELEMS * sizeof(uint32_t);
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
@@ -114,7 +114,7 @@ __device__ __forceinline__ int32_t haar_at(const uint32_t *P, int64_t step, int 
 }
 
 // Workgroup i: output row i.  Rows i, i + a, ... of V (one per row of the
-// template) are read whole into registers first (KV * W <= 8192, so at most
+// template) are read whole into registers first (KV * W <= 12288, so at most
 // NCH chunks of 1024 per row, four elements per thread, one 8-byte load
 // each), then turned into prefixes in LDS chunk by chunk, and the row's
 // features are combined from LDS.  Reading V up to its padded row stride

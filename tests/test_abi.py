@@ -287,8 +287,9 @@ def test_validation_haar(bz):
     F, WS = 0xD00000, 0xF00000
     nb = L.bz_haar_workspace_size(64, 48, 5, 1)
     assert nb == (64 - 5 + 1) * 64 * 2                  # 16-bit column sums only
-    # rows too wide for the row kernel (kv * W > 8192) add 32-bit prefixes
-    assert L.bz_haar_workspace_size(64, 9000, 5, 1) == ((60 * 9024 * 2 + 255) // 256 * 256) + 60 * 9024 * 4
+    # rows too wide for the row kernel (kv * W > 12288) add 32-bit prefixes
+    assert L.bz_haar_workspace_size(64, 13000, 5, 1) == ((60 * 13056 * 2 + 255) // 256 * 256) + 60 * 13056 * 4
+    assert L.bz_haar_workspace_size(64, 4096, 5, 4) == 60 * 4096 * 2   # three rows of 4096 fit
     assert L.bz_haar_workspace_size(4, 48, 5, 1) == 0
     assert L.bz_haar_workspace_size(64, 48, 5, 9) == 0
 

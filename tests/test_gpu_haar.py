@@ -74,5 +74,5 @@ def test_haar_headline_page(bz, kind):
 @pytest.mark.parametrize("kind,H,W,a,b", [("edge_h", 40, 17000, 5, 257), ("line_v", 70, 6000, 20, 9),
                                           ("checker", 50, 8000, 10, 77)])
 def test_haar_rows_wider_than_the_row_kernel(bz, kind, H, W, a, b):
-    # kv * W * 4 bytes above 32 KiB: the prefix-in-place and combine launches
+    # kv * W above 12288 (48 KiB of prefixes): the prefix and combine launches
     check(bz, gen_document(H, W, 600 + kind.__len__(), noise=10.0, stain=True), a, b, kind)
