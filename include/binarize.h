@@ -358,6 +358,19 @@ bz_status bz_soft_sauvola_bwd(const float *I, const float *gy, int B, int H, int
                               float *gI, float *gk, float *gR, void *workspace, size_t ws_bytes,
                               bz_stream stream);
 
+/*
+ * The binary64 window sums S1 = sum I and S2 = sum I^2 that the soft calls
+ * compute internally (Introduction's definition over the clipped window of
+ * Algorithm 1), exported for testing.  The sums run down strips of at most
+ * 32 rows, each primed afresh, so the add-and-subtract recurrence of Section
+ * 3.1 never runs longer than one strip on real-valued data.  I: B float32
+ * images as in bz_soft_sauvola_fwd; S1, S2: binary64, image b at
+ * S + b * H * ld_S, row stride ld_S >= W, 8-byte aligned.  BZ_ERR_RANGE if
+ * one output image spans 2^28 elements or more.
+ */
+bz_status bz_soft_window_sums(const float *I, int B, int H, int W, ptrdiff_t ld, int h, int w, double *S1,
+                              double *S2, ptrdiff_t ld_S, bz_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,13 +49,28 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out: str) -> str:
+    """Compile ``oracle.c`` with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only) into ``out``, for running the pins under the sanitizers
+    (the process must preload the ASan runtime; ``ORACLE_LIB=out`` makes this
+    module load it)."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-Wall", "-o", out, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    path = os.environ.get("ORACLE_LIB")
+    if not path:
+        path = _LIB
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64, f32, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     lib.orc_count.restype = i64

@@ -105,10 +105,57 @@ static uint32_t px(const uint8_t *I, int H, int W, int64_t ld, int i, int j)
     return I[(int64_t)i * ld + j];
 }
 
-/* Algorithm 1's recursive sweep for the window sums, with the accumulator
- * widths of Section 3.3: column sums C in 16 bits, D in 32 bits; the row sums
- * c and d in 32 bits (their differences are exact modulo 2^32).
+/* Section 3.1's recurrences with the accumulator widths of Section 3.3.
+ *
+ * Both passes use one idea: a window sum at position p is the sum at p-1 plus
+ * the element entering the window minus the element leaving it.  Each pass
+ * starts from a window that lies wholly before the image (all zero under the
+ * zero extension of Section 3.2, so its sum is 0 and no priming pass is
+ * needed) and slides into the image one position at a time; outputs are
+ * written only from position 0 on.
+ *
+ * Vertical: the column sums C_j (16 bits: at most 257 values of at most 255)
+ * and D_j (32 bits) of the window rows i-o+1 .. i+u, slid from row -u-1
+ * (rows -u-o .. -1, empty) down to row H-1.
+ * Horizontal: for each row, c and d over columns j-l+1 .. j+r of C and D,
+ * slid from column -r-1 to W-1 (32 bits: every window sum is below 2^32, so
+ * the wrap-around differences are exact).
  * Requires h, w <= 257 (Section 3.3's range argument). */
+
+/* Add the entering row and remove the leaving row of every column sum. */
+static void slide_columns(const uint8_t *I, int H, int W, int64_t ld, int enter, int leave,
+                          uint16_t *C, uint32_t *D)
+{
+    for (int j = 0; j < W; ++j) {
+        uint32_t a = px(I, H, W, ld, enter, j);
+        uint32_t b = px(I, H, W, ld, leave, j);
+        C[j] = (uint16_t)(C[j] + a - b);
+        D[j] = D[j] + a * a - b * b;
+    }
+}
+
+/* The row window sums of one row of column sums: c and d slide along the row
+ * (entering column j+r, leaving column j-l; columns outside the row are 0). */
+static void slide_row(const uint16_t *C, const uint32_t *D, int W, int l, int r, uint32_t *S1,
+                      uint32_t *S2)
+{
+    uint32_t c = 0, d = 0;
+    for (int j = -r; j < W; ++j) {
+        if (j + r < W) {
+            c += C[j + r];
+            d += D[j + r];
+        }
+        if (j - l >= 0) {
+            c -= C[j - l];
+            d -= D[j - l];
+        }
+        if (j >= 0) {
+            S1[j] = c;
+            S2[j] = d;
+        }
+    }
+}
+
 int orc_sums_recursive(const uint8_t *I, int H, int W, int64_t ld, int h, int w,
                        uint32_t *S1, uint32_t *S2)
 {
@@ -118,40 +165,9 @@ int orc_sums_recursive(const uint8_t *I, int H, int W, int64_t ld, int h, int w,
     uint16_t *C = (uint16_t *)calloc((size_t)W, sizeof(uint16_t));
     uint32_t *D = (uint32_t *)calloc((size_t)W, sizeof(uint32_t));
     if (!C || !D) { free(C); free(D); return -2; }
-    /* prime the column sums with rows 0 .. u-1 */
-    for (int j = 0; j < W; ++j) {
-        C[j] = 0;
-        D[j] = 0;
-        for (int i = 0; i < u; ++i) {
-            uint32_t v = px(I, H, W, ld, i, j);
-            C[j] = (uint16_t)(C[j] + v);
-            D[j] += v * v;
-        }
-    }
-    for (int i = 0; i < H; ++i) {
-        /* slide every column sum down by one row */
-        for (int j = 0; j < W; ++j) {
-            uint32_t in = px(I, H, W, ld, i + u, j);
-            uint32_t out = px(I, H, W, ld, i - o, j);
-            C[j] = (uint16_t)(C[j] + in - out);
-            D[j] = D[j] + in * in - out * out;
-        }
-        /* prime the row sums with columns 0 .. r-1 */
-        uint32_t c = 0, d = 0;
-        for (int j = 0; j < r && j < W; ++j) {
-            c += C[j];
-            d += D[j];
-        }
-        for (int j = 0; j < W; ++j) {
-            uint32_t cin = (j + r < W) ? C[j + r] : 0;
-            uint32_t din = (j + r < W) ? D[j + r] : 0;
-            uint32_t cout = (j - l >= 0) ? C[j - l] : 0;
-            uint32_t dout = (j - l >= 0) ? D[j - l] : 0;
-            c = c + cin - cout;
-            d = d + din - dout;
-            S1[(int64_t)i * W + j] = c;
-            S2[(int64_t)i * W + j] = d;
-        }
+    for (int i = -u; i < H; ++i) {
+        slide_columns(I, H, W, ld, i + u, i - o, C, D);
+        if (i >= 0) slide_row(C, D, W, l, r, S1 + (int64_t)i * W, S2 + (int64_t)i * W);
     }
     free(C);
     free(D);

@@ -20,7 +20,7 @@ import torch
 
 __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
-    "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola",
+    "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola", "soft_window_sums",
     "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "window_minmax", "bernsen",
     "binarize_streamed", "haar_features", "HAAR", "LIB_PATH",
 ]
@@ -97,6 +97,8 @@ lib.bz_soft_workspace_size.restype = _SZ
 lib.bz_soft_workspace_size.argtypes = [_I, _I, _I]
 lib.bz_soft_sauvola_fwd.restype = _I
 lib.bz_soft_sauvola_fwd.argtypes = [_P, _I, _I, _I, _PD, _I, _I, _P, _P, _F, _P, _P]
+lib.bz_soft_window_sums.restype = _I
+lib.bz_soft_window_sums.argtypes = [_P, _I, _I, _I, _PD, _I, _I, _P, _P, _PD, _P]
 lib.bz_soft_sauvola_bwd.restype = _I
 lib.bz_soft_sauvola_bwd.argtypes = [_P, _P, _I, _I, _I, _PD, _I, _I, _P, _P, _F, _P, _P, _P, _P,
                                     _SZ, _P]
@@ -520,6 +522,7 @@ class SoftSauvola(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, I, k, R, h, w, tau):
+        shapes = (I.shape, k.shape, R.shape)
         I, k, R, B, H, W = _soft_inputs(I, k, R)
         y = torch.empty_like(I)
         _check(lib.bz_soft_sauvola_fwd(I.data_ptr(), B, H, W, W, int(h), int(w), k.data_ptr(),
@@ -527,7 +530,8 @@ class SoftSauvola(torch.autograd.Function):
                "bz_soft_sauvola_fwd")
         ctx.save_for_backward(I, k, R)
         ctx.win = (int(h), int(w), float(tau))
-        return y
+        ctx.shapes = shapes
+        return y.reshape(shapes[0])
 
     @staticmethod
     def backward(ctx, gy):
@@ -544,7 +548,25 @@ class SoftSauvola(torch.autograd.Function):
                                        R.data_ptr(), float(tau), gI.data_ptr(), gk.data_ptr(),
                                        gR.data_ptr(), ws.data_ptr(), nbytes, _stream(I)),
                "bz_soft_sauvola_bwd")
-        return gI, gk, gR, None, None, None
+        # gradients in the shapes the caller passed (k may be (B, 1), R 0-d)
+        sI, sk, sR = ctx.shapes
+        return gI.reshape(sI), gk.reshape(sk), gR.reshape(sR), None, None, None
+
+
+def soft_window_sums(I: torch.Tensor, h: int, w: int):
+    """The binary64 window sums (S1, S2) the soft calls compute, for a (B, H, W)
+    or (H, W) float32 device tensor (test export of the running sums)."""
+    if I.dim() == 2:
+        I = I.unsqueeze(0)
+    if I.dim() != 3 or I.dtype != torch.float32 or not I.is_cuda:
+        raise ValueError("expected a (B, H, W) float32 device tensor")
+    I = I.contiguous()
+    B, H, W = I.shape
+    S1 = torch.empty((B, H, W), dtype=torch.float64, device=I.device)
+    S2 = torch.empty_like(S1)
+    _check(lib.bz_soft_window_sums(I.data_ptr(), B, H, W, W, int(h), int(w), S1.data_ptr(), S2.data_ptr(), W,
+                                   _stream(I)), "bz_soft_window_sums")
+    return S1, S2
 
 
 def soft_sauvola(I, k, R, h: int, w: int, tau: float = 2.0):

@@ -622,6 +622,24 @@ bz_status bz_soft_sauvola_fwd(const float *I, int B, int H, int W, ptrdiff_t ld,
     return hip_status(launch_soft_fwd(I, B, H, W, ld, h, w, k, R, tau, y, (hipStream_t)stream));
 }
 
+bz_status bz_soft_window_sums(const float *I, int B, int H, int W, ptrdiff_t ld, int h, int w, double *S1,
+                              double *S2, ptrdiff_t ld_S, bz_stream stream)
+{
+    if (I == nullptr || S1 == nullptr || S2 == nullptr) return BZ_ERR_INVALID;
+    if (B < 1 || H < 1 || W < 1 || h < 1 || w < 1 || ld < W || ld_S < W) return BZ_ERR_INVALID;
+    if (h > MAX_WIN || w > MAX_WIN) return BZ_ERR_RANGE;
+    if (!aligned(I, 4) || !aligned(S1, 8) || !aligned(S2, 8)) return BZ_ERR_INVALID;
+    if ((int64_t)B * H * (int64_t)ld > ((int64_t)1 << 40) || (int64_t)B * H * (int64_t)ld_S > ((int64_t)1 << 40))
+        return BZ_ERR_RANGE;
+    // one float32 image spans under 2^31 bytes, and so does one binary64 output image
+    if ((int64_t)(H - 1) * ld + W >= ((int64_t)1 << 29) || (int64_t)(H - 1) * ld_S + W >= ((int64_t)1 << 28))
+        return BZ_ERR_RANGE;
+    const Range in = span(I, B * H, W, ld, 4), a = span(S1, B * H, W, ld_S, 8), b = span(S2, B * H, W, ld_S, 8);
+    if (overlaps(in, a) || overlaps(in, b) || overlaps(a, b)) return BZ_ERR_ALIAS;
+    if (inject_launch_fault()) return BZ_ERR_HIP;
+    return hip_status(launch_soft_sums(I, B, H, W, ld, h, w, S1, S2, ld_S, (hipStream_t)stream));
+}
+
 bz_status bz_soft_sauvola_bwd(const float *I, const float *gy, int B, int H, int W, ptrdiff_t ld,
                               int h, int w, const float *k, const float *R, float tau,
                               float *gI, float *gk, float *gR, void *workspace, size_t ws_bytes,

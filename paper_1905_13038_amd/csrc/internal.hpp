@@ -127,6 +127,9 @@ hipError_t launch_quantile(const QuantJob &job, hipStream_t stream);
 size_t soft_workspace_bytes(int B, int H, int W);
 hipError_t launch_soft_fwd(const float *I, int B, int H, int W, int64_t ld, int h, int w,
                            const float *k, const float *R, float tau, float *y, hipStream_t st);
+// The binary64 window sums of the soft kernels (export for tests).
+hipError_t launch_soft_sums(const float *I, int B, int H, int W, int64_t ld, int h, int w, double *S1,
+                            double *S2, int64_t ldS, hipStream_t st);
 hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W, int64_t ld, int h,
                            int w, const float *k, const float *R, float tau, float *gI, float *gk,
                            float *gR, void *ws, hipStream_t st);

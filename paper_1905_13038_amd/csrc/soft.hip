@@ -17,7 +17,9 @@
 // delta/tau and per-workgroup partials of dL/dk, dL/dR) and ADJ (adjoint
 // sums of G1, G2 -> dL/dI), then k_soft_reduce (fixed-order reduction of
 // the partials, so the k and R gradients are deterministic).  Nothing is
-// saved by the forward: the backward recomputes m and s from I.
+// saved by the forward: the backward recomputes m and s from I.  A fourth
+// phase, SUMS, writes the binary64 window sums themselves (the export that
+// tests the running sums against a direct summation).
 //
 // Layout of a tile (as in the box kernels): lane t owns four adjacent columns
 // for the vertical running sums, loaded as one 16-byte vector per row when
@@ -39,7 +41,7 @@
 namespace bz {
 namespace {
 
-enum Phase { FWD = 0, BWD1 = 1, ADJ = 2 };
+enum Phase { FWD = 0, BWD1 = 1, ADJ = 2, SUMS = 3 };
 
 // Two tile shapes: a workgroup of 4 waves over 1024 halo'd columns (any
 // window up to 257), and a single wave for rows of at most 256 columns (no
@@ -70,6 +72,8 @@ struct SoftArgs {
     float *y;           // FWD output, layout of I
     float *G1, *G2, *dd;  // BWD1 outputs / ADJ inputs: B*H*W, row stride W
     float *gI;          // ADJ output, layout of I
+    double *S1, *S2;    // SUMS outputs: B images of H rows, row stride ldS
+    int64_t ldS;
     double *part;       // BWD1: per-workgroup (dk, dR) partials
     const float *k;     // [B] device
     const float *R;     // [1] device
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
 
     float kb = 0.0f, kR = 0.0f, rRf = 0.0f;
     double kb64 = 0.0, rR64 = 1.0, cR64 = 0.0;
-    if (PH != ADJ) {
+    if (PH == FWD || PH == BWD1) {
         kb = a.k[b];
         kb64 = (double)kb;
         rR64 = 1.0 / (double)a.R[0];
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             Iv[j] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dI, (int)oe[j], (int)soI, 0));
-            if (PH != FWD)
+            if (PH == BWD1 || PH == ADJ)
                 Xv[j] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(dX, (int)oe[j],
                                                                             (int)(PH == ADJ ? soF : soI), 0));
         }
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             Ivs[j] = nIv[j];
-            Xvs[j] = (PH != FWD) ? nXv[j] : 0.0f;
+            Xvs[j] = (PH == BWD1 || PH == ADJ) ? nXv[j] : 0.0f;
         }
         load_epi(y + 1, nIv, nXv);
         {
@@ -396,6 +400,20 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
             const double S1 = P[0][ai0 + 64 * j] - P[0][bi0 + 64 * j];
             const double S2 = P[1][ai0 + 64 * j] - P[1][bi0 + 64 * j];
             const float Iv = Ivs[j];
+            if (PH == SUMS) {
+                // binary64 sums: element offset 8 c of column c (2^31 outside the tile)
+                const uint32_t o8 = oe[j] == SOFF_OUT ? SOFF_OUT : 2u * oe[j];
+                const uint32_t so8 = (uint32_t)(8 * (int64_t)y * a.ldS);
+                const uint32_t sbytes = (uint32_t)(8 * ((int64_t)(H - 1) * a.ldS + W));
+                typedef int v2i __attribute__((ext_vector_type(2)));
+                const v2i w1 = {__double2loint(S1), __double2hiint(S1)};
+                const v2i w2 = {__double2loint(S2), __double2hiint(S2)};
+                __builtin_amdgcn_raw_buffer_store_b64(w1, srsrc(a.S1 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
+                                                      (int)so8, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(w2, srsrc(a.S2 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
+                                                      (int)so8, 0);
+                continue;
+            }
             if (PH == ADJ) {
                 const float g = Xvs[j] + (float)S1 + 2.0f * Iv * (float)S2;
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g), srsrc(a.gI + (int64_t)b * H * ld, img_bytes),
@@ -591,6 +609,31 @@ hipError_t launch_soft_fwd(const float *I, int B, int H, int W, int64_t ld, int 
     a.el = a.l;
     a.er = a.r;
     launch_phase<FWD>(a, B * a.ntx * a.nsy, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_soft_sums(const float *I, int B, int H, int W, int64_t ld, int h, int w, double *S1,
+                            double *S2, int64_t ldS, hipStream_t st)
+{
+    SoftArgs a;
+    memset(&a, 0, sizeof(a));
+    a.I = I;
+    a.S1 = S1;
+    a.S2 = S2;
+    a.ldS = ldS;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    a.ld = ld;
+    a.h = h;
+    a.w = w;
+    a.tau = 1.0f;
+    plan_soft(a);
+    a.eo = a.o;
+    a.eu = a.u;
+    a.el = a.l;
+    a.er = a.r;
+    launch_phase<SUMS>(a, B * a.ntx * a.nsy, st);
     return hipGetLastError();
 }
 

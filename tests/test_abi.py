@@ -92,6 +92,14 @@ def test_validation_other_entry_points(bz):
     assert L.bz_window_quantile(IMG, 64, 64, 64, 15, 15, float("nan"), OUT, 64, None, 64, None) == 1
     assert L.bz_window_quantile(IMG, 64, 64, 64, 15, 15, 0.5, IMG + 1, 64, None, 64, None) == 3
     assert L.bz_window_quantile(IMG, 64, 64, 64, 300, 15, 0.5, OUT, 64, None, 64, None) == 2
+    # the binary64 sums of the soft calls: 8-byte aligned outputs, no overlap
+    big = 0x40000000
+    assert L.bz_soft_window_sums(IMG, 2, 64, 64, 64, 15, 15, big + 4, big + 2 * 64 * 64 * 8, 64, None) == 1
+    assert L.bz_soft_window_sums(IMG, 2, 64, 64, 64, 15, 15, big, big + 64 * 8, 64, None) == 3
+    assert L.bz_soft_window_sums(IMG, 2, 64, 64, 64, 15, 15, big, None, 64, None) == 1
+    assert L.bz_soft_window_sums(IMG, 2, 64, 64, 64, 15, 258, big, big + 2 * 64 * 64 * 8, 64, None) == 2
+    assert L.bz_soft_window_sums(IMG, 2, 64, 64, 64, 15, 15, big, big + 2 * 64 * 64 * 8, 63, None) == 1
+    assert L.bz_soft_window_sums(IMG, 1, 40000, 8, 8, 15, 15, big, big + 2 ** 33, 8000, None) == 2
 
 
 def test_fault_injection_maps_to_hip_error():

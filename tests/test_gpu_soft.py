@@ -65,15 +65,82 @@ def test_full_size_two_images(bz):
     compare(bz, I, k, 128.0, 32, 32, g.astype(np.float64))
 
 
-def test_batch_32_matches_per_image(bz):
-    # the 32-image workload: images 0 and 1 of the full batch give the same
-    # y and gI as a batch of those two alone, and gk is per image
+def _oracle_per_image(I, k, R, h, w, g, workers=8):
+    """oracle.soft_fwd / soft_bwd image by image on a thread pool (the C
+    oracle releases the GIL); the R gradient, a sum over every image and
+    pixel, is the sum of the per-image sums."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(b):
+        ry, _ = oracle.soft_fwd(I[b:b + 1], h, w, k[b:b + 1], R, TAU)
+        rgI, rgk, rgR = oracle.soft_bwd(I[b:b + 1], g[b:b + 1], h, w, k[b:b + 1], R, TAU)
+        return ry[0], rgI[0], rgk[0], rgR
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(one, range(I.shape[0])))
+    ry = np.stack([r[0] for r in res])
+    rgI = np.stack([r[1] for r in res])
+    rgk = np.array([r[2] for r in res])
+    rgR = float(np.sum([r[3] for r in res]))
+    return ry, rgI, rgk, rgR
+
+
+def test_batch_32_against_oracle(bz):
+    # the 32-image workload (32 x 1024 x 1024, h = w = 32, k per image, one R):
+    # y and gI of every image, gk of every image and gR summed over all 32,
+    # against the binary64 oracle
+    print("soft 32-image workload", flush=True)
     I, k, g = soft_batch(B=32)
-    y32, gI32, gk32, gR32 = run(bz, I, k, 128.0, 32, 32, g)
-    y2, gI2, gk2, gR2 = run(bz, I[:2], k[:2], 128.0, 32, 32, g[:2])
-    assert np.array_equal(y32[:2], y2) and np.array_equal(gI32[:2], gI2)
-    assert np.array_equal(gk32[:2], gk2)
-    assert np.isfinite(gR32) and np.all(np.isfinite(gk32))
+    y, gI, gk, gR = run(bz, I, k, 128.0, 32, 32, g)
+    ry, rgI, rgk, rgR = _oracle_per_image(I, k, 128.0, 32, 32, g.astype(np.float64))
+    assert np.max(np.abs(y - ry)) <= Y_ABS, np.max(np.abs(y - ry))
+    for b in range(I.shape[0]):
+        ref = np.max(np.abs(rgI[b]))
+        assert np.max(np.abs(gI[b] - rgI[b])) <= GI_REL * ref, (b, np.max(np.abs(gI[b] - rgI[b])) / ref)
+    assert np.allclose(gk, rgk, rtol=GKR_REL, atol=0), np.max(np.abs(gk - rgk) / np.abs(rgk))
+    assert gR == pytest.approx(rgR, rel=GKR_REL)
+    # images 0 and 1 of the batch give the bits of a batch of those two alone
+    y2, gI2, gk2, _ = run(bz, I[:2], k[:2], 128.0, 32, 32, g[:2])
+    assert np.array_equal(y[:2], y2) and np.array_equal(gI[:2], gI2) and np.array_equal(gk[:2], gk2)
+
+
+def test_gradients_take_the_callers_shapes(bz):
+    # k of shape (B, 1) and a 0-d R: the gradients come back in those shapes
+    I = np.stack([gen_document(40, 48, 90 + b, noise=10, stain=True, dtype=np.float32) for b in range(2)])
+    g = np.random.default_rng(5).standard_normal(I.shape)
+    It = torch.from_numpy(I).cuda().requires_grad_(True)
+    kt = torch.tensor([[0.3], [0.4]], dtype=torch.float32, device="cuda", requires_grad=True)
+    Rt = torch.tensor(128.0, dtype=torch.float32, device="cuda", requires_grad=True)
+    y = bz.soft_sauvola(It, kt, Rt, 7, 9, TAU)
+    (y * torch.from_numpy(g.astype(np.float32)).cuda()).sum().backward()
+    assert kt.grad.shape == (2, 1) and Rt.grad.shape == ()
+    _, rgk, rgR = oracle.soft_bwd(I, g, 7, 9, np.array([0.3, 0.4], np.float32), 128.0, TAU)
+    assert np.allclose(kt.grad.cpu().numpy()[:, 0], rgk, rtol=GKR_REL, atol=0)
+    assert float(Rt.grad) == pytest.approx(rgR, rel=GKR_REL)
+    # one 2-D image with a (1, 1) k
+    I1 = torch.from_numpy(I[0]).cuda().requires_grad_(True)
+    k1 = torch.tensor([[0.3]], dtype=torch.float32, device="cuda", requires_grad=True)
+    y1 = bz.soft_sauvola(I1, k1, Rt, 7, 9, TAU)
+    assert y1.shape == I1.shape
+    y1.sum().backward()
+    assert I1.grad.shape == I1.shape and k1.grad.shape == (1, 1)
+
+
+@pytest.mark.parametrize("B,H,W,h,w", [(2, 1024, 1024, 32, 32), (1, 2000, 40, 31, 31), (1, 1024, 300, 257, 5)])
+def test_running_sums_do_not_drift(bz, B, H, W, h, w):
+    # the binary64 running sums of the soft kernels over full sweeps down
+    # real-valued images agree with the direct binary64 window sums to 1e-12
+    # relative (the add/subtract recurrence restarts with every strip)
+    print("soft sums", B, H, W, h, w, flush=True)
+    I = np.stack([gen_document(H, W, 300 + b, noise=10, stain=True, dtype=np.float32) for b in range(B)])
+    S1, S2 = bz.soft_window_sums(torch.from_numpy(I).cuda(), h, w)
+    S1, S2 = S1.cpu().numpy(), S2.cpu().numpy()
+    for b in range(B):
+        x = I[b].astype(np.float64)
+        r1 = oracle.box_f64(x, h, w)
+        r2 = oracle.box_f64(x * x, h, w)
+        assert np.max(np.abs(S1[b] - r1) / r1) <= 1e-12, np.max(np.abs(S1[b] - r1) / r1)
+        assert np.max(np.abs(S2[b] - r2) / r2) <= 1e-12, np.max(np.abs(S2[b] - r2) / r2)
 
 
 def test_deterministic(bz):

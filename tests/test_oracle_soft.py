@@ -92,6 +92,45 @@ def test_gradients_match_central_differences(h, w):
     assert gR == pytest.approx(fd, rel=1e-6)
 
 
+def test_gradients_match_central_differences_on_64x64_crops():
+    # 64 x 64 crops of the differentiable workload's pages, each crop an
+    # image of its own, at the workload's window h = w = 32 (so most windows
+    # are clipped); central differences in binary64 at every border pixel
+    # and at 256 sampled interior pixels, and for every k and R, against the
+    # oracle's analytic gradient to 1e-6 relative
+    from docgen import soft_batch
+    h = w = 32
+    pages, kk, wr = soft_batch(B=2)
+    rng = np.random.default_rng(64)
+    offs = [(int(rng.integers(0, 1024 - 64)), int(rng.integers(0, 1024 - 64))) for _ in range(2)]
+    I = np.stack([pages[b, i:i + 64, j:j + 64] for b, (i, j) in enumerate(offs)])
+    g = np.stack([wr[b, i:i + 64, j:j + 64] for b, (i, j) in enumerate(offs)]).astype(np.float64)
+    k = kk.astype(np.float64)
+    R = 128.0
+    B, H, W = I.shape
+    gI, gk, gR = oracle.soft_bwd(I, g, h, w, k, R, TAU)
+    border = [(i, j) for i in range(H) for j in range(W) if i in (0, H - 1) or j in (0, W - 1)]
+    inner = [(int(rng.integers(1, H - 1)), int(rng.integers(1, W - 1))) for _ in range(256)]
+    I64 = I.astype(np.float64)
+    for b in range(B):
+        one = lambda X, kb=k[b:b + 1], gb=g[b:b + 1], RR=R: _loss64(X[None], gb, h, w, kb, RR)
+        for (i, j) in border + inner:
+            eps = 1e-3
+            Ip = I64[b].copy()
+            Im = I64[b].copy()
+            Ip[i, j] += eps
+            Im[i, j] -= eps
+            fd = (one(Ip) - one(Im)) / (2 * eps)
+            assert gI[b, i, j] == pytest.approx(fd, rel=1e-6, abs=1e-9), (b, i, j)
+        eps = 1e-6
+        fd = (_loss64(I64[b][None], g[b:b + 1], h, w, k[b:b + 1] + eps, R)
+              - _loss64(I64[b][None], g[b:b + 1], h, w, k[b:b + 1] - eps, R)) / (2 * eps)
+        assert gk[b] == pytest.approx(fd, rel=1e-6)
+    eps = 1e-4
+    fd = (_loss64(I64, g, h, w, k, R + eps) - _loss64(I64, g, h, w, k, R - eps)) / (2 * eps)
+    assert gR == pytest.approx(fd, rel=1e-6)
+
+
 def _loss64(I64, g, h, w, k, R):
     """Loss of a float64 image stack, evaluated with the plain NumPy form of
     the same forward (window sums from the integral images of Section 2)."""

@@ -5,6 +5,8 @@ straight off the Introduction's inequality (pure Python / shifted images), the
 paper's three implementations agreeing (direct, integral images, recursive
 Algorithm 1; Section 4), closed forms and invariants.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -150,9 +152,19 @@ def test_paper_integer_ranges():
     # Section 3.3's accumulator widths: the extreme image (all 255) with the
     # largest window (257 x 257) keeps the 16-bit column sums and the 32-bit
     # window sum of squares exact.
-    assert 255 * 257 == 65535
-    assert 255 * 255 * 257 == 16711425 < 2 ** 32 - 1
-    assert 34833240 > 2 ** 32 / 255
+    # the values Section 3.3 prints (tests/golden/paper_integer_ranges.txt)
+    facts = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_integer_ranges.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                key, val = line.split("=")
+                facts[key.strip()] = val.strip()
+    assert 255 * 257 == int(facts["255*257"]) == 65535
+    assert 255 * 255 * 257 == int(facts["255*255*257"]) < 2 ** 32 - 1
+    assert int(facts["a4_600dpi"]) > 2 ** 32 / 255
+    assert facts["2^32/255"].startswith("%.4f" % (2 ** 32 / 255))
+    # the A4 page at 600 DPI: 8.27 x 11.7 inches
+    assert int(facts["a4_600dpi"]) == round(8.27 * 600) * round(11.7 * 600)
     assert 65025 * 257 * 257 < 2 ** 32
     I = np.full((300, 300), 255, np.uint8)
     r1, r2 = oracle.sums_recursive(I, 257, 257)
