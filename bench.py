@@ -450,9 +450,11 @@ def main():
                     help="skip the other workloads (window sweep, batch, soft, quantiles)")
     ap.add_argument("--pmc", action="store_true",
                     help="counter run: 3 launches + 3 plain 1 GiB copies, no JSON")
-    ap.add_argument("--pmc-workload", choices=("page", "batch", "soft"), default="page",
-                    help="what --pmc launches: the headline page, the 256-page ragged batch "
-                         "(one persistent launch each), or the soft forward + backward")
+    ap.add_argument("--pmc-workload", choices=("page", "mask_only", "batch", "soft", "quantile"),
+                    default="page",
+                    help="what --pmc launches: the headline page (mask + mean + std, or the mask "
+                         "only), the 256-page ragged batch (one persistent launch each), the soft "
+                         "forward + backward, or the 2048x1536 quantiles (q = 0.5, h = 32 and 101)")
     ap.add_argument("--win", type=int, default=75)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -492,6 +494,15 @@ def main():
             for i in range(3):
                 fwd()
                 bwd()
+        elif args.pmc_workload == "mask_only":
+            for i in range(3):
+                img, mask, m, sd = sets[i % len(sets)]
+                bz.sauvola(img, win, win, k=k, R=R, stats=False, mask=mask)
+        elif args.pmc_workload == "quantile":
+            qimg = torch.from_numpy(gen_document(1536, 2048, 3, noise=10.0, stain=True)).to(dev)
+            for qwin in (32, 101):
+                for i in range(3):
+                    bz.window_quantile(qimg, qwin, qwin, 0.5)
         else:
             for i in range(3):
                 step(i)
