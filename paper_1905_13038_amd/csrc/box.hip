@@ -51,19 +51,16 @@ __host__ __device__ constexpr int prefix_row_words(int NT)
 {
     return PREFIX_LPAD + 1 + COLS_PER_LANE * NT + PREFIX_RPAD + 4;
 }
-// LDS of a tile: the prefix rows of a group (S1 and S2 for each of its R
-// rows), the wave totals of those rows, and one staging row per wavefront
-// (two words for each of the wave's 256 epilogue columns: m and s, or S1 and
-// S2), through which the epilogue passes its results from the strided
-// column order of the prefix reads to runs of four adjacent columns per lane
-// for vector stores.
-constexpr int STAGE_WORDS = 2 * 64 * COLS_PER_LANE;  // per wavefront
+// LDS of a tile, for the R rows of a group: the prefix rows (S1 and S2 per
+// row), the gray levels of the rows (one dword per lane), and the wave totals.
+// Gray rows: two sets (alternating by group) of R rows of NT words plus 4
+// words that absorb the writes of halo columns.
+__host__ __device__ constexpr int gray_row_words(int NT) { return NT + 4; }
 __host__ __device__ constexpr int box_buffer_words(int NT)
 {
-    return 2 * ROWS_PER_GROUP * prefix_row_words(NT) + 2 * ROWS_PER_GROUP * MAX_WAVES + STAGE_WORDS * (NT / 64);
+    return 2 * ROWS_PER_GROUP * prefix_row_words(NT) + 2 * ROWS_PER_GROUP * gray_row_words(NT) +
+           2 * ROWS_PER_GROUP * MAX_WAVES;
 }
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Workgroup b is placed on XCD (b mod 8).  Give every XCD a contiguous range
 // of logical tiles so that the halo rows shared by vertically adjacent strips
@@ -206,7 +203,7 @@ __device__ __forceinline__ void add4rows(uint32_t r0, uint32_t r1, uint32_t r2, 
 }
 
 // The binary64 reference decision I < t (each operation rounded once).
-__device__ __forceinline__ bool below_reference(uint32_t I, uint32_t S1, uint32_t S2,
+__device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S1, uint32_t S2,
                                                           int64_t n, int mode, double k64,
                                                           double R64)
 {
@@ -381,58 +378,19 @@ __device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, f
 // within 1 ulp (2u) and the product with 1/n adds 2u, so s is within 4.5u;
 // c1 = k/R and c0 = 1 - k are within u each; q = fma(c1, s, c0) and
 // d = fma(-m, q, I) round once each.  Summed, t32 is within 8.5u mag of the
-// exact t (Sauvola; 6u mag for Niblack), and the binary64 sequence within
+// exact t (Sauvola; 5.5u mag for Niblack), and the binary64 sequence within
 // 2^-50 mag of it.  Where |d| >= 2^-19 mag = 32u mag (a margin of 3.7), the
 // float32 sign is the binary64 one; other pixels are re-decided with the
 // binary64 sequence.  A window of zeros (mag = 0, as for columns past the
 // image) is decided exactly.
 constexpr float GUARD = 1.9073486328125e-06f;  // 2^-19
 
-// Input dwords of one row group: entering rows (y + u) and leaving rows
-// (y - o) of the group's R rows for this lane's four vertical columns, and
-// the centre rows (y) for the lane's four epilogue columns.
+// Input dwords of one row group: entering rows (y + u), leaving rows (y - o)
+// and centre rows (y) of the group's R rows, for this lane's four columns.
 template <int R>
 struct GroupRows {
     uint32_t a[R], b[R], c[R];
 };
-
-// Stores of one output row through descriptor d (row chosen by the scalar
-// offset so).  The lane owns elements e0 .. e0+3 of the tile row; nval of
-// them (0..4) lie inside the tile.  VEC: every row's elements at e0 are
-// aligned for one vector store (4 bytes of mask, 16 bytes of 32-bit values)
-// and nval is 0 or 4.  Otherwise each element is stored alone.  Offsets of
-// elements past the tile are replaced by 2^31, so that the range check drops
-// them.
-template <bool VEC>
-__device__ __forceinline__ void store4_b8(uint32_t v, __amdgpu_buffer_rsrc_t d, uint32_t so, uint32_t e0, int nval)
-{
-    if (VEC) {
-        __builtin_amdgcn_raw_buffer_store_b32(v, d, (int)(nval ? e0 : OFF_OUT), (int)so, STORE_NT);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(v >> (8 * q)), d, (int)(q < nval ? e0 + q : OFF_OUT),
-                                                 (int)so, STORE_NT);
-    }
-}
-// The vector form takes a descriptor of the one row and no scalar offset:
-// on this chip a VALU write to a data register of a 16-byte store issued
-// just before it was measured to change the stored value, and the compiler
-// inserts the wait states that this hazard needs only for stores whose
-// scalar offset is not a register.
-template <bool VEC>
-__device__ __forceinline__ void store4_b32(u32x4 v, __amdgpu_buffer_rsrc_t drow, __amdgpu_buffer_rsrc_t d,
-                                           uint32_t so, uint32_t e0, int nval)
-{
-    if (VEC) {
-        __builtin_amdgcn_raw_buffer_store_b128(v, drow, (int)(nval ? 4u * e0 : OFF_OUT), 0, STORE_NT);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            __builtin_amdgcn_raw_buffer_store_b32(v[q], d, (int)(q < nval ? 4u * (e0 + q) : OFF_OUT), (int)so,
-                                                  STORE_NT);
-    }
-}
 
 // One tile: output columns [x0, x1) of the strip of rows [y0, y1).
 //
@@ -441,44 +399,34 @@ __device__ __forceinline__ void store4_b32(u32x4 v, __amdgpu_buffer_rsrc_t drow,
 //   A  column recurrence for its rows, per-lane prefixes and wavefront scans
 //      (wave totals to LDS),
 //   B  cross-wave combine: the full row prefixes to LDS,
-//   E  epilogue, per row in two steps:
-//      E1  lane t of wave v takes columns 256 v + t + 64 k (k = 0..3), so
-//          that the prefix reads of a wavefront hit consecutive LDS words
-//          (no bank conflicts): window sums, moments, staged in the wave's
-//          LDS staging row;
-//      E2  lane t of wave v takes the four adjacent columns 256 v + 4 t ..
-//          +3 from the staging row: threshold decisions against the gray
-//          levels of those columns (one dword load), and vector stores of
-//          the mask (4 bytes) and of m and s (16 bytes each).
+//   E  epilogue: window sums from the prefixes, moments, threshold, stores.
 // Each phase is written without branches over its rows, so that the compiler
 // can schedule the rows of a group together (the loads of one row under the
 // arithmetic of the other).
 //
 // MS: also write the window mean and standard deviation (always true for
 // MODE_MEANSTD, unused for MODE_SUMS).
-// PAIRS: pairs of row groups per straight-line chunk of the strip loop (the
-// plain kernel unrolls three pairs; the batched kernels one, so that the
-// mixed-batch kernel, which holds every variant, stays one function).
-template <int MODE, bool AL, bool MS, int PAIRS>
+template <int MODE, bool AL, bool MS>
 __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
     constexpr int R = ROWS_PER_GROUP;
     constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK || MODE == MODE_TABLE1);
-    constexpr bool two_out = (MODE == MODE_SUMS || MS);  // the two staged values are outputs
     const int NT = blockDim.x;
     const int PS = prefix_row_words(NT);
-    // prefix row of statistic st (0: S1, 1: S2) for group row r; wave
-    // totals of statistic st for row r; staging row of value v (0: m or S1,
-    // 1: s or S2) of wave w
-    auto prefix_row = [&](int r, int st) { return smem + (2 * r + st) * PS; };
-    auto tot_row = [&](int r, int st) { return smem + 2 * R * PS + (2 * r + st) * MAX_WAVES; };
+    const int BW = box_buffer_words(NT);
+    const int GS = gray_row_words(NT);
+    // prefix row of statistic st (0: S1, 1: S2) for group row r; gray row r
+    // of set g; wave totals of statistic st for row r
+    auto prefix_row = [&](int b, int r, int st) { return smem + b * BW + (2 * r + st) * PS; };
+    auto gray_row = [&](int g, int r) { return smem + 2 * R * PS + (g * R + r) * GS; };
+    auto tot_row = [&](int b, int r, int st) {
+        return smem + b * BW + 2 * R * PS + 2 * R * GS + (2 * r + st) * MAX_WAVES;
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = NT >> 6;
-    uint32_t *stage0 = smem + 2 * R * PS + 2 * R * MAX_WAVES + STAGE_WORDS * wave;
-    uint32_t *stage1 = stage0 + 64 * COLS_PER_LANE;
 
     const int x0 = tx * a.tile_w;
     const int x1 = min(x0 + a.tile_w, a.W);
@@ -486,10 +434,8 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const int y1 = min(y0 + a.strip, a.H);
     const int xh = (tx == 0) ? 0 : x0 - a.halo_l;
     const int H = a.H, W = a.W, o = a.o, u = a.u;
-    // vertical pass: lane owns the four columns cb .. cb+3; the epilogue's
-    // second step owns the four columns ce .. ce+3
+    // vertical pass: lane owns the four columns cb .. cb+3
     const int cb = xh + COLS_PER_LANE * tid;
-    const int ce = x0 + COLS_PER_LANE * tid;
     // The strip reads input rows rlo .. rhi only (its priming rows, then the
     // entering, leaving and centre rows); one descriptor covers them (from
     // the 4-byte boundary at or below the first row in the unaligned form).
@@ -505,10 +451,9 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     const uint32_t rspan = AL ? (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W
                               : (delta + (uint32_t)(rhi - rlo) * ld32 + (uint32_t)W + 3u) & ~3u;
     const LaneRow<AL> ld(cb, W, delta);
-    const LaneRow<AL> lde(ce, W, delta);
     // row `row` if rlo <= row <= rhi (in), else zeros
-    auto row_load = [&](const LaneRow<AL> &lr, int row, bool in) -> uint32_t {
-        return lr.load(rsrc(rbase, in ? rspan : 0u), in ? (uint32_t)(row - rlo) * ld32 : 0u);
+    auto row_load = [&](int row, bool in) -> uint32_t {
+        return ld.load(rsrc(rbase, in ? rspan : 0u), in ? (uint32_t)(row - rlo) * ld32 : 0u);
     };
 
     // zero the left pads (and index 0) of every prefix row once
@@ -517,40 +462,54 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         smem[row * PS + (i - row * (PREFIX_LPAD + 1))] = 0u;
     }
 
-    // E1 columns: wave w covers output columns x0 + 256 w .. x0 + 256 w +
-    // 255, lane t taking columns t, t+64, t+128, t+192 of them.
+    // Epilogue: wave w covers output columns x0 + 256 w .. x0 + 256 w + 255,
+    // lane t taking columns t, t+64, t+128, t+192 of them, so that the prefix
+    // reads of a wavefront hit consecutive LDS words (no bank conflicts) and
+    // each store instruction writes 64 consecutive elements.  Lanes whose
+    // columns lie past the tile compute as the others do; the range checks of
+    // the output descriptors drop their stores.
     const int eo = 256 * wave + lane;  // column k is x0 + eo + 64 k
     const int ec0 = x0 + eo;
     const int ai0 = PREFIX_LPAD + ec0 + a.r - xh + 1;  // prefix word of j + r
     const int bi0 = PREFIX_LPAD + ec0 - a.l - xh + 1;  // prefix word of j - l
     const uint32_t ow = (uint32_t)(x1 - x0);  // output row width of the tile
-    // E2 columns: element offsets e0 .. e0+3 of the tile row, nval of them
-    // inside the tile.
-    const uint32_t e0 = (uint32_t)(COLS_PER_LANE * tid);
-    const int nval = max(0, min(COLS_PER_LANE, (int)ow - (int)e0));
-    const uint32_t last = (uint32_t)(y1 - 1 - y0);  // strip rows - 1
     // Output descriptors cover the strip's rows of the tile (columns x0 ..
     // x1-1), the row chosen by scalar offset (the range check includes it);
-    // none for rows past the strip.
+    // a lane's element offsets are 2^31 for columns outside the tile, so
+    // those stores fail the check.
+    uint32_t o4[4], o1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool in = eo + 64 * k < (int)ow;
+        o4[k] = in ? 4u * (uint32_t)(eo + 64 * k) : OFF_OUT;
+        o1[k] = in ? (uint32_t)(eo + 64 * k) : OFF_OUT;
+    }
+    const uint32_t last = (uint32_t)(y1 - 1 - y0);  // strip rows - 1
+    // descriptor of an output over the strip's rows; none for rows past it
     auto out_rsrc = [&](const void *p, int64_t ldo, int es, bool live) {
         return rsrc((const uint8_t *)p + ((int64_t)y0 * ldo + x0) * es,
                     live ? (uint32_t)es * (last * (uint32_t)ldo + ow) : 0u);
     };
-    // descriptor of the tile's part of output row y alone
-    auto row_rsrc = [&](const void *p, int64_t ldo, int es, int y, bool live) {
-        return rsrc((const uint8_t *)p + ((int64_t)y * ldo + x0) * es, live ? (uint32_t)es * ow : 0u);
-    };
+    // The gray levels of a row, transposed for the epilogue: the dword of
+    // epilogue lane t of wave w holds the levels of its four columns (byte
+    // k: column x0 + 256 w + t + 64 k).  Vertical lane t writes its four
+    // bytes (columns xh + 4t + q, q = 0..3, four consecutive epilogue lanes)
+    // at gbyte + 4 q; halo columns left of x0 go to a spare word.
+    int gbyte;
+    {
+        const int e = COLS_PER_LANE * tid - (x0 - xh);  // a multiple of 4
+        gbyte = (e >= 0) ? 4 * (64 * (e >> 8) + (e & 63)) + ((e & 255) >> 6) : 4 * NT;
+    }
 
-    // Window sizes of the E1 columns for rows whose window lies inside the
-    // image vertically (nr = h), and their reciprocals.
+    // Window sizes of the epilogue columns for rows whose window lies inside
+    // the image vertically (nr = h), and their reciprocals.
     double ndh[4];
     float rnh[4];
-    int nck[4];  // clipped window widths
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int j = ec0 + 64 * k;
-        nck[k] = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
-        ndh[k] = (double)a.h * (double)nck[k];
+        const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
+        ndh[k] = (double)a.h * (double)nc;
         rnh[k] = 1.0f / (float)ndh[k];
     }
     // Guard of the float32 decision, near iff |d| < GUARD * mag'.  Sauvola:
@@ -594,7 +553,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         if (row <= p1) {  // fewer than PB rows left: rows past p1 read zero
             uint32_t v[PB];
 #pragma unroll
-            for (int q = 0; q < PB; ++q) v[q] = row_load(ld, row + q, row + q <= p1);
+            for (int q = 0; q < PB; ++q) v[q] = row_load(row + q, row + q <= p1);
 #pragma unroll
             for (int g = 0; g < PB / 4; ++g)
                 if (row + 4 * g <= p1) add4rows(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], C, D);
@@ -602,45 +561,44 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
     }
 
     // ---- the row groups ----
-    // A group's rows are loaded two groups ahead, into the registers of the
-    // group two before it (two register sets, the loop unrolled by two, so
-    // that no copy of a register with a load in flight is needed): the
-    // entering and leaving rows right after that group's column recurrence
-    // has consumed them, before its stores; the centre rows after its
-    // epilogue.  One wait counter tracks loads and stores in issue order, so
-    // a wait for rows also waits for the stores issued before them: those of
-    // the group three before (entering and leaving rows) or two before
-    // (centre rows), long drained.
-    GroupRows<R> X0, X1;
-    auto load_ab = [&](int yg, GroupRows<R> &g) {
+    // The next group's rows are loaded during a group and waited for at its
+    // end: one wait counter tracks loads and stores in issue order, so the
+    // wait is placed after the group's stores rather than before them.
+    GroupRows<R> X;
+    auto load_group = [&](int yg, GroupRows<R> &g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             // rows past the strip load zeros: the recurrence leaves C, D as they are
             const int ra = yg + r + u, rb = yg + r - o;
             const bool on = yg + r < y1;
-            g.a[r] = row_load(ld, ra, on && ra <= rhi);
-            g.b[r] = row_load(ld, rb, on && rb >= rlo);
+            g.a[r] = row_load(ra, on && ra <= rhi);
+            g.b[r] = row_load(rb, on && rb >= rlo);
+            if (need_i) g.c[r] = row_load(yg + r, yg + r <= rhi);
         }
     };
-    auto load_c = [&](int yg, GroupRows<R> &g) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (need_i) g.c[r] = row_load(lde, yg + r, yg + r < y1 && yg + r <= rhi);
-    };
-    auto settle_ab = [&](GroupRows<R> &g) {
+    auto settle_group = [&](GroupRows<R> &g) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             settle(g.a[r]);
             settle(g.b[r]);
+            if (need_i) settle(g.c[r]);
         }
     };
 
     uint32_t pc[R][4], pd[R][4], sc[R], sd[R];
     // A: column recurrence, per-lane prefixes and wave scans of group rows
     // yg .. yg+R-1
-    auto phase_A = [&](const GroupRows<R> &cur) {
+    auto phase_A = [&](int gs, const GroupRows<R> &cur) {
+        const int b = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            // the centre row's gray levels, for the epilogue's column order
+            // (read back by lanes of this same wavefront only)
+            if (need_i) {
+                uint8_t *gw = (uint8_t *)gray_row(gs, r) + gbyte;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gw[4 * q] = (uint8_t)byte_of(cur.c[r], q);
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int ak = (int)byte_of(cur.a[r], k), bk = (int)byte_of(cur.b[r], k);
@@ -659,22 +617,22 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             sc[r] = wave_scan(pc[r][3]);
             sd[r] = wave_scan(pd[r][3]);
             if (lane == 63) {
-                tot_row(r, 0)[wave] = sc[r];
-                tot_row(r, 1)[wave] = sd[r];
+                tot_row(b, r, 0)[wave] = sc[r];
+                tot_row(b, r, 1)[wave] = sd[r];
             }
         }
     };
-    // B: offsets of the wave totals, full row prefixes to LDS.  The scan over
-    // the first 16 lanes gives wave w's offset at lane w-1 and the tile
-    // totals (tc, td) at lane nwaves-1; lanes at or above nwaves never feed
-    // those, so they read any total.  Branch-free, so that it can interleave
-    // with the epilogue.
+    // B: offsets of the wave totals, full row prefixes into buffer b.  The
+    // scan over the first 16 lanes gives wave w's offset at lane w-1 and the
+    // tile totals (tc, td) at lane nwaves-1; lanes at or above nwaves never
+    // feed those, so they read any total.  Branch-free, so that it can
+    // interleave with the epilogue.
     uint32_t tc[R], td[R];
-    auto phase_B = [&]() {
+    auto phase_B = [&](int b) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint32_t wc = row_scan16(tot_row(r, 0)[lane & 15]);
-            const uint32_t wd = row_scan16(tot_row(r, 1)[lane & 15]);
+            const uint32_t wc = row_scan16(tot_row(b, r, 0)[lane & 15]);
+            const uint32_t wd = row_scan16(tot_row(b, r, 1)[lane & 15]);
             const int wl = max(wave - 1, 0);
             uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)wc, wl);
             uint32_t od = (uint32_t)__builtin_amdgcn_readlane((int)wd, wl);
@@ -683,21 +641,21 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             tc[r] = (uint32_t)__builtin_amdgcn_readlane((int)wc, nwaves - 1);
             td[r] = (uint32_t)__builtin_amdgcn_readlane((int)wd, nwaves - 1);
             const uint32_t ec_ = sc[r] - pc[r][3] + oc, ed_ = sd[r] - pd[r][3] + od;
-            uint32_t *prc = prefix_row(r, 0) + PREFIX_LPAD + 1;  // index 1
-            uint32_t *prd = prefix_row(r, 1) + PREFIX_LPAD + 1;
+            uint32_t *prc = prefix_row(b, r, 0) + PREFIX_LPAD + 1;  // index 1
+            uint32_t *prd = prefix_row(b, r, 1) + PREFIX_LPAD + 1;
             *(uint4 *)(prc + COLS_PER_LANE * tid) =
                 make_uint4(pc[r][0] + ec_, pc[r][1] + ec_, pc[r][2] + ec_, pc[r][3] + ec_);
             *(uint4 *)(prd + COLS_PER_LANE * tid) =
                 make_uint4(pd[r][0] + ed_, pd[r][1] + ed_, pd[r][2] + ed_, pd[r][3] + ed_);
         }
     };
-    // right pads: repeat the tile totals (last wave)
-    auto pads_B = [&]() {
+    // right pads of buffer b: repeat the tile totals (last wave)
+    auto pads_B = [&](int b) {
         if (wave == nwaves - 1) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                uint32_t *prc = prefix_row(r, 0) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
-                uint32_t *prd = prefix_row(r, 1) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
+                uint32_t *prc = prefix_row(b, r, 0) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
+                uint32_t *prd = prefix_row(b, r, 1) + PREFIX_LPAD + 1 + COLS_PER_LANE * NT;
 #pragma unroll
                 for (int q = 0; q < PREFIX_RPAD / 64; ++q) {
                     prc[64 * q + lane] = tc[r];
@@ -707,58 +665,58 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         }
     };
 
-    // Statistics of E1 column k of group row r: window sums, then n and the
-    // moments from the window size n and its reciprocal rn; n*S2 - S1^2 is
-    // formed exactly in binary64 (every term is an integer below 2^53).
+    // Statistics of epilogue column k of group row r from buffer b: window
+    // sums, then n = nr * nc and the moments; n*S2 - S1^2 is formed exactly
+    // in binary64 (every term is an integer below 2^53).
     struct ColStats {
         uint32_t S1, S2;
-        float m, s;
+        double n;
+        float m, s, rn;
     };
-    auto col_stats = [&](int r, int k, double n, float rn) -> ColStats {
+    auto col_stats = [&](int b, int r, int k, int y, bool interior) -> ColStats {
         ColStats c;
-        const uint32_t *pa = prefix_row(r, 0) + ai0 + 64 * k;
-        const uint32_t *pb = prefix_row(r, 0) + bi0 + 64 * k;
+        const uint32_t *pa = prefix_row(b, r, 0) + ai0 + 64 * k;
+        const uint32_t *pb = prefix_row(b, r, 0) + bi0 + 64 * k;
         c.S1 = pa[0] - pb[0];
         c.S2 = pa[PS] - pb[PS];
+        float rn;
+        if (interior) {
+            c.n = (k == 0) ? ndh[0] : (k == 1) ? ndh[1] : (k == 2) ? ndh[2] : ndh[3];
+            rn = (k == 0) ? rnh[0] : (k == 1) ? rnh[1] : (k == 2) ? rnh[2] : rnh[3];
+        } else {
+            const int nr = max(min(y + u, H - 1) - max(y - o, -1), 1);
+            const int j = ec0 + 64 * k;
+            const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
+            c.n = (double)nr * (double)nc;
+            rn = 1.0f / (float)c.n;
+        }
+        c.rn = rn;
         c.m = (float)c.S1 * rn;
         const double s1d = (double)c.S1;
-        const double vn = __builtin_fma(n, (double)c.S2, -(s1d * s1d));
+        const double vn = __builtin_fma(c.n, (double)c.S2, -(s1d * s1d));
         c.s = __builtin_amdgcn_sqrtf((float)vn) * rn;
         return c;
-    };
-    // Window sums and count of column j of group row r (any column of the
-    // tile's epilogue range, any row).
-    auto stats_at = [&](int r, int j, int y, uint32_t &S1, uint32_t &S2) -> int64_t {
-        const uint32_t *pa = prefix_row(r, 0) + PREFIX_LPAD + j + a.r - xh + 1;
-        const uint32_t *pb = prefix_row(r, 0) + PREFIX_LPAD + j - a.l - xh + 1;
-        S1 = pa[0] - pb[0];
-        S2 = pa[PS] - pb[PS];
-        const int nr = max(min(y + u, H - 1) - max(y - o, -1), 1);
-        const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
-        return (int64_t)nr * (int64_t)nc;
     };
     // float32 decision: d = I - t with the exact sign of I - t (the mask bit
     // is its sign bit; d is +0 when I equals t) and the guard metric nm
     // (the pixel is near the threshold when nm < 0)
-    auto decide = [&](float m, float s, float gv, float &d, float &nm) {
+    auto decide = [&](const ColStats &c, float gv, float &d, float &nm) {
         if (MODE == MODE_SAUVOLA) {
-            const float q = __builtin_fmaf(a.c1, s, a.c0);  // 1 + k (s/R - 1)
-            d = __builtin_fmaf(-m, q, gv);
-            nm = __builtin_fmaf(gA, m, __builtin_fabsf(d));
+            const float q = __builtin_fmaf(a.c1, c.s, a.c0);  // 1 + k (s/R - 1)
+            d = __builtin_fmaf(-c.m, q, gv);
+            nm = __builtin_fmaf(gA, c.m, __builtin_fabsf(d));
         } else {
-            d = gv - __builtin_fmaf(a.c1, s, m);
-            nm = __builtin_fmaf(gA, __builtin_fmaf(a.kabs, s, m), __builtin_fabsf(d));
+            d = gv - __builtin_fmaf(a.c1, c.s, c.m);
+            nm = __builtin_fmaf(gA, __builtin_fmaf(a.kabs, c.s, c.m), __builtin_fabsf(d));
         }
     };
 
-    // E: epilogue of the group whose rows start at yg (centre rows in cc).
-    // One code path for interior and border rows (only the window sizes
-    // differ, and their branch holds no memory access): the compiler's
-    // bookkeeping of the loads in flight loses track at the join of two
-    // paths that both store.
-    auto phase_E = [&](int yg, const uint32_t (&cc)[R], bool interior) {
-        uint32_t mbits[R];    // mask bytes of the lane's E2 columns, per row
-        float nmv[R][4];      // their guard metrics (near when < 0)
+    // E: epilogue of the group whose rows start at yg, from buffer b and
+    // gray set gs
+    auto phase_E = [&](int yg, int b, int gs, auto interior_tag) {
+        constexpr bool interior = decltype(interior_tag)::value;
+        uint32_t bits[R][4];
+        float nmv[R][4];  // guard metrics (near when < 0)
         float nmin = 1.0f;
         uint32_t t1near = 0;  // Table 1: pixels inside the float32 guard
 #pragma unroll
@@ -766,103 +724,91 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             const int y = yg + r;
             const bool live = y < y1;  // rows past the strip store nothing
             const uint32_t dy = (uint32_t)(y - y0);
-            // E1: statistics of the strided columns, staged
-            {
-                double nk[4];
-                float rnk[4];
+            ColStats c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = col_stats(b, r, k, y, interior);
+            if (MODE == MODE_SUMS) {
+                const uint32_t so = 4u * dy * (uint32_t)a.ldS;
+                const __amdgpu_buffer_rsrc_t d1 = out_rsrc(a.S1, a.ldS, 4, live);
+                const __amdgpu_buffer_rsrc_t d2 = out_rsrc(a.S2, a.ldS, 4, live);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    nk[k] = ndh[k];
-                    rnk[k] = rnh[k];
+                    __builtin_amdgcn_raw_buffer_store_b32(c[k].S1, d1, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(c[k].S2, d2, (int)o4[k], (int)so, STORE_NT);
                 }
-                if (!interior) {  // rows whose window is clipped vertically
-                    const int nr = max(min(y + u, H - 1) - max(y - o, -1), 1);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        nk[k] = (double)nr * (double)nck[k];
-                        rnk[k] = 1.0f / (float)nk[k];
-                    }
-                }
-                ColStats c[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = col_stats(r, k, nk[k], rnk[k]);
+                continue;
+            }
+            if (MS) {
+                const uint32_t so = 4u * dy * (uint32_t)a.ldMS;
+                const __amdgpu_buffer_rsrc_t dm = out_rsrc(a.mean, a.ldMS, 4, live);
+                const __amdgpu_buffer_rsrc_t ds = out_rsrc(a.stdv, a.ldMS, 4, live);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    stage0[lane + 64 * k] = (MODE == MODE_SUMS) ? c[k].S1 : __float_as_uint(c[k].m);
-                    stage1[lane + 64 * k] = (MODE == MODE_SUMS) ? c[k].S2 : __float_as_uint(c[k].s);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c[k].m), dm, (int)o4[k], (int)so, STORE_NT);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c[k].s), ds, (int)o4[k], (int)so, STORE_NT);
                 }
             }
-            // E2: the lane's four adjacent columns (the staging row is this
-            // wavefront's own, and LDS accesses of a wavefront complete in
-            // order, so no barrier is needed)
-            const u32x4 v0 = *(const u32x4 *)(stage0 + COLS_PER_LANE * lane);
-            const u32x4 v1 = *(const u32x4 *)(stage1 + COLS_PER_LANE * lane);
-            if (two_out) {
-                const void *p0 = (MODE == MODE_SUMS) ? (const void *)a.S1 : (const void *)a.mean;
-                const void *p1 = (MODE == MODE_SUMS) ? (const void *)a.S2 : (const void *)a.stdv;
-                const int64_t ldo = (MODE == MODE_SUMS) ? a.ldS : a.ldMS;
-                const uint32_t so = 4u * dy * (uint32_t)ldo;
-                store4_b32<AL>(v0, row_rsrc(p0, ldo, 4, y, live), out_rsrc(p0, ldo, 4, live), so, e0, nval);
-                store4_b32<AL>(v1, row_rsrc(p1, ldo, 4, y, live), out_rsrc(p1, ldo, 4, live), so, e0, nval);
-            }
-            if (!need_i) continue;
-            uint32_t mb = 0;
+            if (MODE == MODE_MEANSTD) continue;
+            const uint32_t gw = gray_row(gs, r)[tid];  // byte k: column ec0 + 64 k (this lane's word)
+            if (MODE == MODE_TABLE1) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float m = __uint_as_float(v0[q]), s = __uint_as_float(v1[q]);
-                const float gv = (float)byte_of(cc[r], q);
+                for (int k = 0; k < 4; ++k) {
+                    float d, g;
+                    table1_fast(t1f, c[k].m, c[k].s, c[k].rn, (float)byte_of(gw, k), d, g);
+                    bits[r][k] = d < 0.0f ? 1u : 0u;
+                    if (a.force_ref || !(fabsf(d) > g)) t1near |= 1u << (4 * r + k);
+                }
+                continue;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
                 float d;
-                if (MODE == MODE_TABLE1) {
-                    const int j = ce + q;
-                    const int nr = max(min(y + u, H - 1) - max(y - o, -1), 1);
-                    const int nc = max(min(j + a.r, W - 1) - max(j - a.l, -1), 1);
-                    const float rn = 1.0f / (float)((double)nr * (double)nc);
-                    float g;
-                    table1_fast(t1f, m, s, rn, gv, d, g);
-                    mb |= (d < 0.0f ? 1u : 0u) << (8 * q);
-                    if (a.force_ref || !(fabsf(d) > g)) t1near |= 1u << (4 * r + q);
-                } else {
-                    float nm;
-                    decide(m, s, gv, d, nm);
-                    mb |= (__float_as_uint(d) >> 31) << (8 * q);
-                    nmv[r][q] = nm;
-                    nmin = __builtin_fminf(nmin, nm);
-                }
+                decide(c[k], (float)byte_of(gw, k), d, nmv[r][k]);
+                bits[r][k] = __float_as_uint(d) >> 31;
+                nmin = __builtin_fminf(nmin, nmv[r][k]);
             }
-            mbits[r] = mb;
         }
         if (!need_i) return;
-        // pixels within the guard (rare): re-decided with the binary64
-        // sequence, statistics recomputed from the prefix rows
-        uint32_t near = t1near;
-        if (MODE != MODE_TABLE1 && (a.force_ref || nmin < 0.0f)) {
+        // pixels within the guard: re-decided with the binary64 sequence
+        // (rare; statistics recomputed from LDS, one call site)
+        if (MODE == MODE_TABLE1) {
+            // pixels inside the guard: the binary64 sequence (statistics
+            // recomputed from LDS)
+            while (t1near != 0) {
+                const int i = __builtin_ctz(t1near);
+                t1near &= t1near - 1;
+                const int r = i >> 2, k = i & 3;
+                const ColStats c = col_stats(b, r, k, yg + r, false);
+                const uint32_t gv = ((const uint8_t *)gray_row(gs, r))[4 * tid + k];
+                const uint32_t bit = table1_below(gv, c.S1, c.S2, (int64_t)c.n, a.rule, a.tp[0], a.tp[1],
+                                                  a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
+                                         ? 1u
+                                         : 0u;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) bits[rr][kk] = (i == 4 * rr + kk) ? bit : bits[rr][kk];
+            }
+        } else if (a.force_ref || nmin < 0.0f) {
+            uint32_t near = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (a.force_ref || nmv[r][q] < 0.0f) near |= 1u << (4 * r + q);
-        }
-        // columns past the tile store nothing
-        near &= 0x11111111u * ((1u << nval) - 1u) & ((1u << (4 * R)) - 1u);
-        while (near != 0) {
-            const int i = __builtin_ctz(near);
-            near &= near - 1;
-            const int r = i >> 2, q = i & 3;
-            uint32_t S1, S2;
-            const int64_t n = stats_at(r, ce + q, yg + r, S1, S2);
-            uint32_t cw = cc[0];  // (no dynamic register indexing)
+                for (int k = 0; k < 4; ++k)
+                    if (a.force_ref || nmv[r][k] < 0.0f) near |= 1u << (4 * r + k);
+            while (near != 0) {
+                const int i = __builtin_ctz(near);
+                near &= near - 1;
+                const int r = i >> 2, k = i & 3;
+                const ColStats c = col_stats(b, r, k, yg + r, false);
+                const uint32_t gv = ((const uint8_t *)gray_row(gs, r))[4 * tid + k];
+                const uint32_t bit =
+                    below_reference(gv, c.S1, c.S2, (int64_t)c.n, MODE, a.k64, a.R64) ? 1u : 0u;
 #pragma unroll
-            for (int rr = 1; rr < R; ++rr) cw = (r == rr) ? cc[rr] : cw;
-            const uint32_t gv = (cw >> (8 * q)) & 0xffu;
-            bool below;
-            if (MODE == MODE_TABLE1)
-                below = table1_below(gv, S1, S2, n, a.rule, a.tp[0], a.tp[1], a.tp[2], a.tp[3], a.tp[4], gL,
-                                     gM, gS);
-            else
-                below = below_reference(gv, S1, S2, n, MODE, a.k64, a.R64);
-            const uint32_t sel = 0xffu << (8 * q), bit = (below ? 1u : 0u) << (8 * q);
+                for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) mbits[rr] = (r == rr) ? ((mbits[rr] & ~sel) | bit) : mbits[rr];
+                    for (int kk = 0; kk < 4; ++kk) bits[rr][kk] = (i == 4 * rr + kk) ? bit : bits[rr][kk];
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -871,45 +817,31 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             // uniform so the stores take them from scalar registers)
             const __amdgpu_buffer_rsrc_t dk = out_rsrc(a.mask, a.ldM, 1, y < y1);
             const uint32_t so = uniform((uint32_t)(y - y0) * (uint32_t)a.ldM);
-            store4_b8<AL>(mbits[r], dk, so, e0, nval);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits[r][k], dk, (int)o1[k], (int)so, STORE_NT);
         }
     };
 
     // ---- the groups of the strip ----
-    auto group = [&](int yg, GroupRows<R> &X) {
-        settle_ab(X);  // this group's entering and leaving rows
-        phase_A(X);
-        load_ab(yg + 2 * R, X);  // those of the group after next
+    load_group(y0, X);
+    settle_group(X);
+    int gs = 0;  // gray set of the group (alternates: a wave may still read
+                 // the previous group's set while another writes the next)
+    for (int yg = y0; yg < y1; yg += R, gs ^= 1) {
+        const GroupRows<R> cur = X;
+        if (yg + R < y1) load_group(yg + R, X);  // prefetch the next group
+        phase_A(gs, cur);
         __syncthreads();
-        phase_B();
-        pads_B();
+        phase_B(0);
+        pads_B(0);
         __syncthreads();
+        settle_group(X);  // the next group's rows, before this group's stores
         // rows whose windows lie vertically inside the image use the cached
         // window sizes
         const bool interior = (yg - o >= -1) && (yg + R - 1 + u <= H - 1);
-        phase_E(yg, X.c, interior);
-        load_c(yg + 2 * R, X);  // centre rows of the group after next
-    };
-    // The groups run in chunks of 2 PAIRS, straight-line code with an exit
-    // after each group.  (The compiler's wait for loads at the top of a loop
-    // covers every load and store in flight, which would stall on the
-    // group prefetched last; inside a chunk each wait covers only the rows
-    // it needs.)
-    load_ab(y0, X0);
-    load_c(y0, X0);
-    load_ab(y0 + R, X1);
-    load_c(y0 + R, X1);
-    for (int yg = y0;;) {
-#pragma unroll
-        for (int i = 0; i < PAIRS; ++i) {
-            group(yg, X0);
-            yg += R;
-            if (yg >= y1) break;
-            group(yg, X1);
-            yg += R;
-            if (yg >= y1) break;
-        }
-        if (yg >= y1) break;
+        if (interior) phase_E(yg, 0, gs, std::true_type{});
+        else phase_E(yg, 0, gs, std::false_type{});
     }
 }
 
@@ -919,17 +851,17 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
 template <int MODE, bool AL, bool MS, bool BIG>
 __global__ __launch_bounds__(MAX_THREADS) void k_box(BoxJob a)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t smem[];  // 16-byte LDS accesses
+    extern __shared__ uint32_t smem[];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = L / a.nsy;
-    box_tile<MODE, AL, MS, MODE == MODE_TABLE1 ? 1 : 3>(a, tx, L - tx * a.nsy, smem);
+    box_tile<MODE, AL, MS>(a, tx, L - tx * a.nsy, smem);
 }
 
 template <int MODE, bool MS>
 __device__ __forceinline__ void batched_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
-    if (a.aligned) box_tile<MODE, true, MS, 1>(a, tx, sy, smem);
-    else box_tile<MODE, false, MS, 1>(a, tx, sy, smem);
+    if (a.aligned) box_tile<MODE, true, MS>(a, tx, sy, smem);
+    else box_tile<MODE, false, MS>(a, tx, sy, smem);
 }
 
 // A word of the batch workspace, the same for every lane.  The workspace is
@@ -997,8 +929,8 @@ __device__ __forceinline__ void batched_loop(BatchHeader *hdr, TileFn tile)
 // Any mix of Sauvola/Niblack, alignment and mean/std outputs.
 __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t smem[];  // 16-byte LDS accesses
-    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) __attribute__((always_inline)) {
+    extern __shared__ uint32_t smem[];
+    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) {
         const bool ms = a.mean != nullptr;
         if (a.mode == MODE_SAUVOLA) {
             if (ms) batched_tile<MODE_SAUVOLA, true>(a, tx, sy, smem);
@@ -1015,10 +947,8 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_box_batched(BatchHeader *hdr)
 template <int MODE, bool AL, bool MS>
 __global__ __launch_bounds__(BATCH_THREADS, 4) void k_box_batched_v(BatchHeader *hdr)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t smem[];  // 16-byte LDS accesses
-    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) __attribute__((always_inline)) {
-        box_tile<MODE, AL, MS, AL ? 3 : 1>(a, tx, sy, smem);
-    });
+    extern __shared__ uint32_t smem[];
+    batched_loop(hdr, [&](const BoxJob &a, int tx, int sy) { box_tile<MODE, AL, MS>(a, tx, sy, smem); });
 }
 
 // Kernel of batch variant v (-1: mixed batch).
@@ -1122,17 +1052,6 @@ void plan_box(BoxJob &a, int strip_override, int threads_override)
     if (strip > cap) strip = (int)std::max<int64_t>(cap, 1);
     a.strip = strip;
     a.nsy = (a.H + strip - 1) / strip;
-    // Vector stores: a tile's rows start at multiples of 4 columns, so with
-    // W a multiple of 4 the mask takes dword stores when its base and row
-    // stride are multiples of 4 bytes, and the float (or uint32) outputs
-    // take 16-byte stores when their bases are 16-byte aligned and their row
-    // strides multiples of 4 elements.  Jobs that allow them all run the
-    // aligned variant; the others store element by element.
-    auto al = [](const void *p, uintptr_t n) { return ((uintptr_t)p % n) == 0; };
-    const bool vm = a.mask == nullptr || (al(a.mask, 4) && a.ldM % 4 == 0);
-    const bool vf = a.mean == nullptr || (al(a.mean, 16) && al(a.stdv, 16) && a.ldMS % 4 == 0);
-    const bool vs = a.S1 == nullptr || (al(a.S1, 16) && al(a.S2, 16) && a.ldS % 4 == 0);
-    a.aligned = a.aligned && vm && vf && vs;
 }
 
 hipError_t launch_box(const BoxJob &a, hipStream_t stream)

@@ -58,8 +58,7 @@ struct BoxJob {
     int threads;           // block size (multiple of 64, <= 1024)
     int tile_w, ntx, halo_l;
     int strip, nsy;
-    int aligned;           // all pointers/strides allow vector access (input: 4-byte rows
-                           // and W a multiple of 4; outputs checked by plan_box)
+    int aligned;           // all pointers/strides allow vector access
     int force_ref;         // decide every pixel with the binary64 sequence (testing)
     // MODE_TABLE1: the rule, its parameters and the image's global statistics
     // (device record; null for rules that use none)
