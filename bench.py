@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Gpix/s Sauvola 4096×3072 w=75 (% HBM peak); batched & fwd+bwd vs plain"
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_sauvola_4096x3072_w75.txt")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "counters_sauvola_4096x3072_w75.txt")
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-ops per second, in T
 
 
 def kernel_source_hash() -> str:
@@ -61,17 +63,54 @@ def read_traffic(launch_px: int):
         return None
 
 
+def read_counter(key: str):
+    """A per-pixel figure from the committed counter summary of the headline
+    kernel, or None if missing or taken on other kernel source."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    vals = {}
+    for line in open(PROFILE_COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[key])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(I, h, w, k, R, seconds):
+    """The CPU oracle on the same page: one thread, then row bands (each with
+    its halo rows, re-priming its column sums) on a thread pool of up to 16
+    of the host's cores.  `value` is the pool's rate."""
     import oracle
-    mpix, reps, dt = oracle.time_recursive_sauvola(I, h, w, k, R, min_seconds=seconds)
+    mpix1, reps1, dt1 = oracle.time_recursive_sauvola(I, h, w, k, R, min_seconds=seconds / 2)
+    nproc = os.cpu_count() or 1
+    threads = max(1, min(16, nproc))
+    mpixn, repsn, dtn = oracle.time_recursive_sauvola_bands(I, h, w, k, R, threads, min_seconds=seconds / 2)
     return {
-        "value": round(mpix / 1000.0, 6),
+        "value": round(mpixn / 1000.0, 6),
         "unit": "Gpix/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": "%d full passes of the %dx%d page (Algorithm 1 sweep + binary64 threshold, "
-                  "one thread, %.1f s, %s)" % (reps, I.shape[1], I.shape[0], dt,
-                                               platform.processor() or platform.machine()),
+        "sample": "%d full passes of the %dx%d page on %d threads (row bands with their halo rows; "
+                  "Algorithm 1 sweep + binary64 threshold, %.1f s) and %d on one thread (%.1f s)"
+                  % (repsn, I.shape[1], I.shape[0], threads, dtn, reps1, dt1),
+        "single_thread_value": round(mpix1 / 1000.0, 6),
+        "nproc": nproc,
+        "cpu_model": cpu_model(),
     }
 
 
@@ -224,7 +263,32 @@ def extras(sets, host, args):
 
     def mask_only():
         us = _loop_us(lambda i: page_call("sauvola", 75, False, i), 30)
-        return {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1), "bytes_per_px": 2}
+        res = {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1), "bytes_per_px": 2,
+               "hbm_frac": round(2.0 * px / us / 1e3 / HBM_PEAK_GBS, 4)}
+        ops = read_counter("mask_only_valu_lane_ops_per_px")
+        if ops is not None:
+            # VALU roofline: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s
+            res["valu_lane_ops_per_px"] = ops
+            res["valu_frac"] = round(ops * px / us / 1e6 / VALU_PEAK_TOPS, 4)
+        return res
+
+    def transposed():
+        # the headline page transposed: 3072 wide, 4096 tall
+        Ht, Wt = W, H
+        img = torch.from_numpy(np.ascontiguousarray(host.T)).to(sets[0][0].device)
+        outs = [(torch.empty((Ht, Wt), dtype=torch.uint8, device=img.device),
+                 torch.empty((Ht, Wt), dtype=torch.float32, device=img.device),
+                 torch.empty((Ht, Wt), dtype=torch.float32, device=img.device)) for _ in range(4)]
+
+        def f(i):
+            mk, m, sd = outs[i % 4]
+            rc = lib.bz_sauvola(img.data_ptr(), Ht, Wt, Wt, 75, 75, 0.5, 128.0, mk.data_ptr(), Wt,
+                                m.data_ptr(), sd.data_ptr(), Wt, st)
+            if rc != 0:
+                raise RuntimeError("status %d" % rc)
+        us = _loop_us(f, 30)
+        return {"us": round(us, 2), "Gpix_s": round(px / us / 1e3, 1),
+                "hbm_frac": round(10.0 * px / us / 1e3 / HBM_PEAK_GBS, 4), "shape_HxW": [Ht, Wt]}
 
     def mean_std():
         def f(i):
@@ -424,6 +488,7 @@ def extras(sets, host, args):
 
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
+    guarded("sauvola_w75_transposed_3072x4096", transposed)
     guarded("mean_std_w75", mean_std)
     guarded("sauvola_w75_cache_warm", cache_warm)
     guarded("write_floor_9Bpx", fill_floor)
@@ -535,6 +600,9 @@ def main():
     # per step; the queue stays full, so the per-step time is the kernel's
     # duration plus the device-side gap between consecutive dispatches).
     launch_ms = total_ms / args.steps
+    # and the median of single launches, each between two events (the
+    # events' own overhead included)
+    median_us = _timeit(step, 50) if not args.pmc else None
 
     px = H * W
     ms_per_step = total_ms / args.steps
@@ -562,6 +630,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_box<MODE_SAUVOLA>",
                      "launch_us_mean": round(launch_ms * 1e3, 3),
+                     "launch_us_median_single": round(median_us, 3),
                      "launch_us_source": "HIP events around the timed region's back-to-back launches",
                      "algorithmic_bytes": int(alg_bytes)},
     }

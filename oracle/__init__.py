@@ -439,3 +439,84 @@ def time_recursive_sauvola(I, h: int, w: int, k: float, R: float, min_seconds: f
         if dt >= min_seconds:
             break
     return reps * H * W / dt / 1e6, reps, dt
+
+
+
+def _bands(I, h: int, w: int, threads: int):
+    """Row bands for a threaded run: output rows y0..y1-1 of each band, and
+    its input rows a..e-1 (the window's halo, o - 1 rows above and u below,
+    clipped to the image), copied as an image of their own."""
+    I, H, W, ld = _img(I)
+    o, u, _, _ = extents(h, w)
+    edges = [H * t // threads for t in range(threads + 1)]
+    out = []
+    for t in range(threads):
+        y0, y1 = edges[t], edges[t + 1]
+        if y1 > y0:
+            a, e = max(y0 - o + 1, 0), min(y1 + u, H)
+            out.append((y0, y1, a, np.ascontiguousarray(I[a:e])))
+    return out
+
+
+class _BandRun:
+    """The oracle's Algorithm 1 sweep and canonical Sauvola threshold on one
+    band, with buffers reused across runs."""
+
+    def __init__(self, sub, h, w, k, R):
+        self.sub, self.h, self.w = sub, h, w
+        self.k, self.R = float(np.float32(k)), float(np.float32(R))
+        Hb, W = sub.shape
+        self.S1 = np.empty((Hb, W), np.uint32)
+        self.S2 = np.empty((Hb, W), np.uint32)
+        self.S1w = np.empty((Hb, W), np.uint64)
+        self.S2w = np.empty((Hb, W), np.uint64)
+        self.m = np.empty((Hb, W), np.float64)
+        self.s = np.empty((Hb, W), np.float64)
+        self.mask = np.empty((Hb, W), np.uint8)
+
+    def __call__(self):
+        lib = _load()
+        Hb, W = self.sub.shape
+        lib.orc_sums_recursive(_ptr(self.sub), Hb, W, W, self.h, self.w, _ptr(self.S1), _ptr(self.S2))
+        np.copyto(self.S1w, self.S1)
+        np.copyto(self.S2w, self.S2)
+        lib.orc_threshold(_ptr(self.sub), Hb, W, W, self.h, self.w, _ptr(self.S1w), _ptr(self.S2w),
+                          SAUVOLA, self.k, self.R, _ptr(self.m), _ptr(self.s), None, _ptr(self.mask))
+
+
+def sauvola_bands(I, h: int, w: int, k: float, R: float, threads: int):
+    """The Sauvola mask computed band by band on a thread pool (each band an
+    image of its own with its halo rows): equal to ``sauvola(I, ...)["mask"]``,
+    since every output row's window lies inside its band's input rows or is
+    clipped at the same image border."""
+    from concurrent.futures import ThreadPoolExecutor
+    I = np.ascontiguousarray(I, dtype=np.uint8)
+    bands = _bands(I, h, w, threads)
+    runs = [_BandRun(sub, h, w, k, R) for (_, _, _, sub) in bands]
+    with ThreadPoolExecutor(max_workers=len(runs)) as ex:
+        list(ex.map(lambda r: r(), runs))
+    mask = np.empty(I.shape, np.uint8)
+    for (y0, y1, a, _), r in zip(bands, runs):
+        mask[y0:y1] = r.mask[y0 - a:y1 - a]
+    return mask
+
+
+def time_recursive_sauvola_bands(I, h: int, w: int, k: float, R: float, threads: int,
+                                 min_seconds: float = 10.0):
+    """Wall-clock Mpix/s of ``sauvola_bands``' work (the oracle calls of
+    ``time_recursive_sauvola`` on ``threads`` row bands at once; the C calls
+    release the interpreter lock).  Returns (mpix_per_s, repeats, seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    I = np.ascontiguousarray(I, dtype=np.uint8)
+    H, W = I.shape
+    runs = [_BandRun(sub, h, w, k, R) for (_, _, _, sub) in _bands(I, h, w, threads)]
+    reps = 0
+    with ThreadPoolExecutor(max_workers=len(runs)) as ex:
+        t0 = time.perf_counter()
+        while True:
+            list(ex.map(lambda r: r(), runs))
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds:
+                break
+    return reps * H * W / dt / 1e6, reps, dt

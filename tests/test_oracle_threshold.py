@@ -150,3 +150,12 @@ def test_niblack_negative_k_exact():
     _exact_agreement(I, 5, 5, oracle.NIBLACK, -0.2)
     res = oracle.niblack(I, 5, 5, k=-0.2)
     assert np.allclose(res["t"], res["m"] - np.float64(np.float32(0.2)) * res["s"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("h,w,threads", [(75, 75, 7), (15, 9, 16), (32, 4, 3), (151, 31, 5), (4, 4, 40)])
+def test_banded_runs_equal_the_whole_image(h, w, threads):
+    # the CPU baseline runs the oracle on row bands with their halo rows on a
+    # thread pool; its masks must equal the whole-image call
+    I = gen_document(300, 257, 11, noise=10, stain=True)
+    whole = oracle.sauvola(I, h, w, k=0.5, R=128.0)["mask"]
+    assert np.array_equal(oracle.sauvola_bands(I, h, w, 0.5, 128.0, threads), whole)
