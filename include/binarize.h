@@ -140,6 +140,25 @@ bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int 
                      uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
                      void *workspace, size_t ws_bytes, bz_stream stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it): bz_bernsen without a workspace
+ * argument.  The 16-bit field of the two passes lives in a device array of
+ * the library, fixed at 32 MiB per GPU (held until the process ends), so
+ * H W must not exceed bz_bernsen_noalloc_max_pixels() (16,777,216; larger
+ * images return BZ_ERR_WORKSPACE).  The call allocates nothing; its first
+ * call on a device looks up that device's array (BZ_ERR_HIP if the lookup
+ * fails).  Every call on one GPU shares the array: calls that overlap in
+ * time on one GPU (on different streams) race and give undefined outputs;
+ * calls ordered on one stream do not.  No part of the array needs to start
+ * at zero (the first pass writes every entry the second pass reads).
+ * Arguments, validation and results are those of bz_bernsen.
+ */
+size_t bz_bernsen_noalloc_max_pixels(void);
+bz_status bz_bernsen_noalloc(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int contrast_min,
+                             uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
+                             bz_stream stream);
+
 /* Thresholding rule of a batched item. */
 enum { BZ_METHOD_SAUVOLA = 1, BZ_METHOD_NIBLACK = 2 };
 

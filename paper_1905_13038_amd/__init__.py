@@ -60,6 +60,10 @@ lib.bz_window_minmax.restype = _I
 lib.bz_window_minmax.argtypes = [_P, _I, _I, _PD, _I, _I, _P, _P, _PD, _P, _SZ, _P]
 lib.bz_bernsen.restype = _I
 lib.bz_bernsen.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _P, _PD, _P, _SZ, _P]
+lib.bz_bernsen_noalloc.restype = _I
+lib.bz_bernsen_noalloc.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _P, _PD, _P]
+lib.bz_bernsen_noalloc_max_pixels.restype = _SZ
+lib.bz_bernsen_noalloc_max_pixels.argtypes = []
 lib.bz_global_stats.restype = _I
 lib.bz_global_stats.argtypes = [_P, _I, _I, _PD, _P, _P]
 lib.bz_threshold.restype = _I

@@ -5,6 +5,8 @@
 #include "haar.hpp"
 #include "internal.hpp"
 
+#include <mutex>
+
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -506,6 +508,53 @@ bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int 
     if (contrast_min < 0 || contrast_min > 256) return BZ_ERR_INVALID;
     return extremes_call(I, H, W, ld_I, h, w, contrast_min, mask, ld_mask, mn, mx, ld_mm, workspace, ws_bytes,
                          stream);
+}
+
+// ---- Bernsen's rule with no allocation and no workspace argument ----
+// The field of the two passes lives in a file-scope device array of fixed
+// size; its device address is looked up once per device, with that device
+// current, on the first call there.  In host code the array's name is not a
+// device address: only the looked-up pointer is passed to kernels.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;  // 32 MiB: 16 Mpx of 16-bit field
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];  // per device, set once
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+bz_status scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return BZ_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return BZ_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BZ_OK;
+}
+}  // namespace
+
+size_t bz_bernsen_noalloc_max_pixels(void) { return NOALLOC_SCRATCH_BYTES / sizeof(uint16_t); }
+
+bz_status bz_bernsen_noalloc(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, int contrast_min,
+                             uint8_t *mask, ptrdiff_t ld_mask, uint8_t *mn, uint8_t *mx, ptrdiff_t ld_mm,
+                             bz_stream stream)
+{
+    if (mask == nullptr) return BZ_ERR_INVALID;
+    if (contrast_min < 0 || contrast_min > 256) return BZ_ERR_INVALID;
+    const bz_status st = check_minmax(I, H, W, ld_I, h, w, mn, mx, ld_mm, mask, ld_mask);
+    if (st != BZ_OK) return st;
+    if (extremes_workspace_bytes(H, W) > NOALLOC_SCRATCH_BYTES) return BZ_ERR_WORKSPACE;
+    void *ws = nullptr;
+    const bz_status sa = scratch_address(&ws);
+    if (sa != BZ_OK) return sa;
+    return extremes_call(I, H, W, ld_I, h, w, contrast_min, mask, ld_mask, mn, mx, ld_mm, ws,
+                         NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t bz_batched_workspace_size(int count)
