@@ -255,8 +255,10 @@ size_t bz_haar_workspace_size(int H, int W, int a, int kind);
  * F[i * ld_F + j] = sum over cells (m, n) of sign(m, n) times the sum of I
  * over rows i + m a .. i + (m+1) a - 1 and columns j + n b .. j + (n+1) b - 1,
  * for 0 <= i < H - kv a + 1 and 0 <= j < W - kh b + 1 (exact int32).  The
- * cell sums come from sliding column sums of a rows (Section 3.1's
- * recursion) and row prefixes of them.  1 <= a, b <= 257 (BZ_ERR_RANGE
+ * cell sums come from sliding column sums (Section 3.1's recursion) and row
+ * prefixes of them: in one launch, with the workspace unused, for 4-byte
+ * aligned rows (I and ld_I) and kh b <= 256; otherwise in two or three
+ * launches through the workspace.  1 <= a, b <= 257 (BZ_ERR_RANGE
  * above); a template larger than the image is BZ_ERR_INVALID.  F: int32,
  * 4-byte aligned, ld_F >= W - kh b + 1.  workspace: at least
  * bz_haar_workspace_size(H, W, a, kind) bytes, 256-byte aligned, overlapping

@@ -18,6 +18,7 @@
 // Two entry kernels share the tile body: k_box (one tile per workgroup, tiles
 // mapped XCD-contiguously) and k_box_batched (a persistent grid that claims
 // tiles of many images from an atomic counter, largest tiles first).
+#include "device.hpp"
 #include "internal.hpp"
 
 #include <math.h>
@@ -62,66 +63,13 @@ __host__ __device__ constexpr int box_buffer_words(int NT)
            2 * ROWS_PER_GROUP * MAX_WAVES;
 }
 
-// Workgroup b is placed on XCD (b mod 8).  Give every XCD a contiguous range
-// of logical tiles so that the halo rows shared by vertically adjacent strips
-// stay in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int n)
-{
-    const int q = n >> 3, rem = n & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v)
-{
-    // lanes without a DPP source (or in rows masked off) read 0
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
-}
-
-// Inclusive prefix sum over the 64 lanes of a wavefront (Hillis-Steele within
-// rows of 16 lanes, then the row_bcast steps that carry row totals forward).
-__device__ __forceinline__ uint32_t wave_scan(uint32_t v)
-{
-    v += dpp_or_zero<0x111, 0xf>(v);  // row_shr:1
-    v += dpp_or_zero<0x112, 0xf>(v);  // row_shr:2
-    v += dpp_or_zero<0x114, 0xf>(v);  // row_shr:4
-    v += dpp_or_zero<0x118, 0xf>(v);  // row_shr:8
-    v += dpp_or_zero<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
-    v += dpp_or_zero<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
-    return v;
-}
-
-// Inclusive prefix sum over the first 16 lanes (row 0).
-__device__ __forceinline__ uint32_t row_scan16(uint32_t v)
-{
-    v += dpp_or_zero<0x111, 0xf>(v);
-    v += dpp_or_zero<0x112, 0xf>(v);
-    v += dpp_or_zero<0x114, 0xf>(v);
-    v += dpp_or_zero<0x118, 0xf>(v);
-    return v;
-}
-
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
-
-// Raw buffer resources (base, num_records in bytes, stride 0).  Accesses at
-// offsets at or beyond num_records read zero and drop stores in hardware, so
-// image borders, out-of-image rows and lanes outside a tile need no per-lane
-// branch or select.  The last descriptor word is the raw-buffer format value
-// for gfx9-family chips.
-constexpr int RSRC_FLAGS = 0x00020000;
 
 // Cache policy of the output stores: non-temporal.  Outputs are written once
 // and not read back by the kernel; streaming them keeps the L2 for the input
 // rows the strips share and raised the store rate of this access pattern by
 // about 40% in measurements on MI355X.
 constexpr int STORE_NT = 2;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
-                                             RSRC_FLAGS);
-}
 
 // Reads the four pixels of a lane (columns cb .. cb+3, cb a multiple of 4) of
 // one row through a descriptor d over whole rows from a first row r0, the row
@@ -300,11 +248,16 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
 // threshold against the binary64 one, relative to the magnitude mag of its
 // terms, are about: Wolf 12u, NICK 7u, Rais 25u, Phansalkar (13 + 4|q m|)u
 // of |m| C with C = 1 + |p| e^(-qm) + |k|(1 + s/R), and Feng
-// (10 + 5 |g|)u (one powf, x^(1+g) = x x^g).  The guard G mag takes 2^-18 (64u) for Wolf and NICK,
-// 2^-17 for Phansalkar (mag scaled by 1 + |q m|), 2^-16 for Rais and 2^-15
-// for Feng (mag scaled by 2 + |g|): a factor of 5 or more over the bounds.
-// Where |I - t32| > G mag the float32 and binary64 decisions agree; other
-// pixels, and any non-finite value, go to table1_below.
+// (11 + |g|(6.1 + 2.1 |log2 x|))u with x = s/R.  For Feng, x^g is
+// 2^(g log2 x) from the native log2 and exp2, which, checked over every
+// float32 input in the ranges used, are within 2u max(1, |log2 x|)
+// (absolute) and 1.42u (relative); x is within 4u, so x^g is within
+// (1.5 + |g|(6.1 + 2.1 |log2 x|))u.  The guard G mag takes 2^-18 (64u) for
+// Wolf and NICK, 2^-17 for Phansalkar (mag scaled by 1 + |q m|), 2^-16 for
+// Rais and 2^-19 for Feng (mag scaled by 2 + |g|(1 + |log2 x|)): a factor of
+// 5 or more over the bounds.  Where |I - t32| > G mag the float32 and
+// binary64 decisions agree; other pixels, and any non-finite value, go to
+// table1_below.
 struct T1Fast {
     int rule;
     float p0, p1, p2, p3;
@@ -312,6 +265,7 @@ struct T1Fast {
     float L;    // global minimum
     float MS;   // M S
     float G;    // guard factor
+    float pow0; // Feng: 0^g (0 for g > 0, 1 for g = 0, infinity for g < 0)
 };
 
 __device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, double L, double M, double S)
@@ -326,10 +280,11 @@ __device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, dou
     f.rR = (float)(1.0 / R);
     f.L = (float)L;
     f.MS = (float)M * (float)S;
+    f.pow0 = tp[3] > 0.0 ? 0.0f : tp[3] == 0.0 ? 1.0f : __builtin_inff();
     f.G = rule == T1_WOLF || rule == T1_NICK ? 0x1p-18f
           : rule == T1_PHANSALKAR             ? 0x1p-17f
           : rule == T1_RAIS                   ? 0x1p-16f
-                                              : 0x1p-15f;
+                                              : 0x1p-19f;
     return f;
 }
 
@@ -361,11 +316,21 @@ __device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, f
         t = m * c;
         mag = fabsf(m) * (1.0f + fabsf(f.p0) * ex + fabsf(f.p2) * (1.0f + s * f.rR)) * (1.0f + fabsf(qm));
     } else {  // T1_FENG
+        // x^g = 2^(g log2 x) with the native log2 and exp2; x^(1+g) = x x^g.
+        // A flat window (x = 0) takes pow's value (0, 1, or infinity for
+        // g < 0, which sends it to the reference); an exponent beyond 120 in
+        // magnitude (a result outside the normal range, or log2 of a
+        // subnormal) gives NaN, which does too.
         const float x = s * f.rR;
-        const float x0 = powf(x, f.p3), x1 = x * x0;  // x^(1+g) = x x^g
+        const float lg = __builtin_amdgcn_logf(x);
+        const float e = f.p3 * lg;
+        const float p = __builtin_amdgcn_exp2f(e);
+        const float x0 = x == 0.0f ? f.pow0 : (fabsf(e) <= 120.0f ? p : __builtin_nanf(""));
+        const float x1 = x * x0;
+        const float al = x == 0.0f ? 0.0f : fabsf(lg);
         t = f.p0 * m + f.p1 * x1 * (m - f.L) + f.p2 * x0 * f.L;
         mag = (fabsf(f.p0 * m) + fabsf(f.p1) * x1 * (fabsf(m) + fabsf(f.L)) + fabsf(f.p2) * x0 * fabsf(f.L)) *
-              (2.0f + fabsf(f.p3));
+              (2.0f + fabsf(f.p3) * (1.0f + al));
     }
     d = I - t;
     g = f.G * mag;

@@ -19,7 +19,28 @@
 //   them.)
 // Every cell sum is below 2^32 (255 * 257 * 257), so the wrap-around
 // differences are exact, and |F| <= 2 * 255 * 257 * 257 < 2^31.
+//
+// The five templates have alternating signs down and across (the checker is
+// the product of the two), which allows a fused form of one launch and no
+// workspace, k_haar_fused, used for 4-byte aligned rows and templates up to
+// 256 columns wide:
+//   G[i][x] = sum over m < kv of (-1)^m (sum of I over rows i + m a ..
+//             i + m a + a - 1 of column x),
+//   F[i][j] = sum over n < kh of (-1)^n (sum of G[i] over columns j + n b ..
+//             j + n b + b - 1).
+// Down a strip G slides with kv + 1 row reads per step (Section 3.1's column
+// recursion over the signed stack of cells):
+//   G[i+1][x] - G[i][x] = sum over j = 0 .. kv of c_j I[i + j a][x],
+//   c_0 = -1, c_j = 2 (-1)^(j-1) for 0 < j < kv, c_kv = (-1)^(kv-1),
+// and along the row F is a signed sum of kh + 1 entries of the inclusive
+// prefix P of G[i] (P[-1] = 0), with the same coefficients:
+//   F[i][j] = sum over n = 0 .. kh of c_n P[j + n b - 1].
+#include "device.hpp"
 #include "haar.hpp"
+
+#include <stdlib.h>
+
+#include <algorithm>
 
 namespace bz {
 namespace {
@@ -31,6 +52,9 @@ constexpr int HAAR_STRIP = HAAR_ROWS;
 // row is loaded whole before its scan)
 constexpr int HAAR_ROW_ELEMS = 12288;
 constexpr size_t HAAR_ROW_LDS = HAAR_ROW_ELEMS * sizeof(uint32_t);
+// output rows per group of k_haar_fused: the next group's row loads are in
+// flight while a group is processed
+constexpr int HAAR_GROUP = 4;
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
@@ -202,6 +226,149 @@ __global__ __launch_bounds__(HAAR_THREADS) void k_haar_combine(const uint32_t *_
     F[(int64_t)i * ldF + j] = haar_at(P + (int64_t)i * ldP, (int64_t)a * ldP, j, b, kv, kh, neg);
 }
 
+// Coefficient c_j of the slide and of the prefix combination for a stack of
+// k alternating cells (see the head of this file).
+__host__ __device__ constexpr int haar_coef(int j, int k)
+{
+    return j == 0 ? -1 : j == k ? ((k - 1) & 1 ? -1 : 1) : ((j - 1) & 1 ? -2 : 2);
+}
+
+// Wavefront (tx, sy), one per 64-thread workgroup in XCD order: the tile of
+// TWC = 256 NDW columns of G from x0 = tx * step (step <= TWC - (kh b - 1),
+// a multiple of 4) gives the outputs x0 .. x0 + step - 1 of output rows
+// i0 = sy * S .. min(i0 + S, Hf) - 1.  Lane t holds G of columns 4t .. 4t+3
+// (+ 256 d for its d-th dword).  Rows are read through a descriptor per row
+// from column x0 with (W - x0) bytes rounded up to a dword: the aligned dword
+// holding the row's last byte is readable memory, and columns past W only
+// reach prefix entries that no kept output reads (output j reads G columns up
+// to j + kh b - 1 <= W - 1).  Per output row: the lane's inclusive prefix
+// over its four columns, a wavefront scan of the lane totals, the row's
+// prefix to LDS (P[c] at entry 4 + c, entry 3 the zero P[-1], so that a lane
+// writes its four entries as one aligned 16-byte store), then lane t forms
+// the outputs t + 64 k from LDS and stores them (the descriptor over the
+// output row drops columns past Wf, and an offset past it those past the
+// tile's step).  The stores take the default cache policy: tile rows start
+// at any 4-byte offset of a cache line, and neighbouring tiles complete each
+// other's partial lines in L2 (non-temporal stores measured 1.2 to 1.5x
+// slower for 12 x 12 cells on the 4096 x 3072 page).  Two LDS buffers
+// alternate by row, so one barrier per row suffices, and rows go in groups of
+// HAAR_GROUP: the slide's row loads of the next group are issued before a
+// group's work, so that their latency is hidden behind it (processing two rows
+// per barrier, with their scans interleaved, measured slower).
+template <int KV, int KH, int NDW>
+__global__ __launch_bounds__(64) void k_haar_fused(const uint8_t *__restrict__ I, int64_t ldI, int W, int a, int b,
+                                                   int Hf, int Wf, int step, int ntx, int S, int nsy,
+                                                   int32_t *__restrict__ F, int64_t ldF)
+{
+    constexpr int TWC = 256 * NDW;
+    constexpr int NC = 4 * NDW;  // columns per lane
+    __shared__ __align__(16) uint32_t Q[2][TWC + 4];
+    const int lane = threadIdx.x;
+    const int L = xcd_remap(blockIdx.x, ntx * nsy);
+    const int tx = L / nsy, sy = L - tx * nsy;
+    const int x0 = tx * step;
+    const int i0 = sy * S, i1 = min(i0 + S, Hf);
+    const uint32_t nrec = (uint32_t)((W - x0 + 3) & ~3);
+    const uint8_t *I0 = I + x0;
+    auto row_rsrc = [&](int row) { return rsrc(I0 + (int64_t)row * ldI, nrec); };
+    auto load = [&](const __amdgpu_buffer_rsrc_t &d, int q) {
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane + 256 * q, 0, 0);
+    };
+
+    // G of row i0: the signed sum of the kv a rows below it
+    uint32_t g[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) g[c] = 0u;
+#pragma unroll
+    for (int m = 0; m < KV; ++m) {
+        const int r0 = i0 + m * a;
+#pragma unroll 4
+        for (int r = 0; r < a; ++r) {
+            const __amdgpu_buffer_rsrc_t d = row_rsrc(r0 + r);
+#pragma unroll
+            for (int q = 0; q < NDW; ++q) {
+                const uint32_t v = load(d, q);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t e = (v >> (8 * c)) & 0xffu;
+                    g[4 * q + c] = (m & 1) ? g[4 * q + c] - e : g[4 * q + c] + e;
+                }
+            }
+        }
+    }
+
+    const __amdgpu_buffer_rsrc_t none = rsrc(I, 0u);
+    const uint32_t Fbytes = 4u * (uint32_t)(Wf - x0);
+    // the slide's rows of a group of HAAR_GROUP output rows ig .. (row i's
+    // rows for G[i+1]; none for the strip's last row or rows past it)
+    uint32_t cur[HAAR_GROUP][KV + 1][NDW], nxt[HAAR_GROUP][KV + 1][NDW];
+    auto load_group = [&](int ig, uint32_t(&sl)[HAAR_GROUP][KV + 1][NDW]) {
+#pragma unroll
+        for (int r = 0; r < HAAR_GROUP; ++r) {
+            const bool in = ig + r + 1 < i1;
+#pragma unroll
+            for (int j = 0; j <= KV; ++j) {
+                const __amdgpu_buffer_rsrc_t d = in ? row_rsrc(ig + r + j * a) : none;
+#pragma unroll
+                for (int q = 0; q < NDW; ++q) sl[r][j][q] = load(d, q);
+            }
+        }
+    };
+    load_group(i0, cur);
+    int buf = 0;
+    for (int ig = i0; ig < i1; ig += HAAR_GROUP) {
+        load_group(ig + HAAR_GROUP, nxt);  // in flight during this group
+#pragma unroll
+        for (int r = 0; r < HAAR_GROUP; ++r) {
+            const int i = ig + r;
+            if (i >= i1) break;
+            // prefix of G[i] over the tile into Q[buf][4 ..] (Q[buf][3] = 0)
+            uint32_t carry = 0u;
+#pragma unroll
+            for (int q = 0; q < NDW; ++q) {
+                uint32_t p[4];
+                p[0] = g[4 * q];
+#pragma unroll
+                for (int c = 1; c < 4; ++c) p[c] = p[c - 1] + g[4 * q + c];
+                const uint32_t incl = wave_scan(p[3]);
+                const uint32_t excl = carry + incl - p[3];
+                *(uint4 *)&Q[buf][4 + 256 * q + 4 * lane] = make_uint4(excl + p[0], excl + p[1], excl + p[2],
+                                                                        excl + p[3]);
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            }
+            if (lane == 0) Q[buf][3] = 0u;
+            __syncthreads();
+            // outputs t + 64 k of row i
+            const __amdgpu_buffer_rsrc_t fo = rsrc(F + (int64_t)i * ldF + x0, Fbytes);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const int col = lane + 64 * k;
+                uint32_t f = 0u;
+#pragma unroll
+                for (int n = 0; n <= KH; ++n) f += (uint32_t)haar_coef(n, KH) * Q[buf][3 + min(col + n * b, TWC)];
+                const uint32_t off = col < step ? 4u * (uint32_t)col : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(f, fo, (int)off, 0, 0);
+            }
+            buf ^= 1;
+            // G[i+1]
+#pragma unroll
+            for (int j = 0; j <= KV; ++j) {
+                const int cj = haar_coef(j, KV);
+#pragma unroll
+                for (int q = 0; q < NDW; ++q)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) g[4 * q + c] += (uint32_t)cj * ((cur[r][j][q] >> (8 * c)) & 0xffu);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < HAAR_GROUP; ++r)
+#pragma unroll
+            for (int j = 0; j <= KV; ++j)
+#pragma unroll
+                for (int q = 0; q < NDW; ++q) cur[r][j][q] = nxt[r][j][q];
+    }
+}
+
 }  // namespace
 
 int64_t haar_ld(int W) { return ((int64_t)W + 63) / 64 * 64; }
@@ -220,9 +387,75 @@ size_t haar_workspace_bytes(int H, int W, int a, int kv)
     return haar_fused(W, kv) ? v : v + (size_t)(H - a + 1) * (size_t)haar_ld(W) * sizeof(uint32_t);
 }
 
+// Negative cells of the alternating kv x kh template: (m + n) odd.
+static uint32_t alternating(int kv, int kh)
+{
+    uint32_t neg = 0;
+    for (int m = 0; m < kv; ++m)
+        for (int n = 0; n < kh; ++n)
+            if ((m + n) & 1) neg |= 1u << (m * kh + n);
+    return neg;
+}
+
+template <int KV, int KH>
+static void launch_fused(int ndw, dim3 grid, hipStream_t stream, const uint8_t *I, int64_t ldI, int W, int a, int b,
+                         int Hf, int Wf, int step, int ntx, int S, int nsy, int32_t *F, int64_t ldF)
+{
+    if (ndw == 1)
+        hipLaunchKernelGGL((k_haar_fused<KV, KH, 1>), grid, dim3(64), 0, stream, I, ldI, W, a, b, Hf, Wf, step, ntx,
+                           S, nsy, F, ldF);
+    else
+        hipLaunchKernelGGL((k_haar_fused<KV, KH, 2>), grid, dim3(64), 0, stream, I, ldI, W, a, b, Hf, Wf, step, ntx,
+                           S, nsy, F, ldF);
+}
+
+bool haar_fused_plan(const uint8_t *I, int64_t ldI, int H, int W, int a, int b, int kv, int kh, uint32_t neg,
+                     HaarPlan &p)
+{
+    const char *e = getenv("BZ_HAAR_FUSED");
+    if (e && atoi(e) == 0) return false;
+    if (((uintptr_t)I & 3u) != 0 || (ldI & 3) != 0 || neg != alternating(kv, kh)) return false;
+    if (!((kv == 1 && kh == 2) || (kv == 2 && kh == 1) || (kv == 1 && kh == 3) || (kv == 3 && kh == 1) ||
+          (kv == 2 && kh == 2)))
+        return false;
+    const int halo = kh * b - 1;
+    if (halo > 255) return false;
+    p.Hf = H - kv * a + 1;
+    p.Wf = W - kh * b + 1;
+    p.ndw = halo <= 31 ? 1 : 2;
+    e = getenv("BZ_HAAR_NDW");
+    if (e && (atoi(e) == 1 || atoi(e) == 2) && 256 * atoi(e) - halo >= 4) p.ndw = atoi(e);
+    p.step = (256 * p.ndw - halo) & ~3;
+    p.ntx = (p.Wf + p.step - 1) / p.step;
+    // strips: about an eighth of the kv a priming rows (8 to 64), halved
+    // while the grid has fewer than 2048 wavefronts (down to 4 rows);
+    // BZ_HAAR_STRIP overrides
+    int S = std::min(64, std::max(8, (kv * a + 7) / 8));
+    while (S > 4 && (int64_t)p.ntx * ((p.Hf + S - 1) / S) < 2048) S /= 2;
+    e = getenv("BZ_HAAR_STRIP");
+    if (e && atoi(e) > 0) S = atoi(e);
+    p.S = std::min(S, p.Hf);
+    p.nsy = (p.Hf + p.S - 1) / p.S;
+    return (int64_t)p.ntx * p.nsy < ((int64_t)1 << 31) / 64;
+}
+
 hipError_t launch_haar(const uint8_t *I, int64_t ldI, int H, int W, int a, int b, int kv, int kh, uint32_t neg,
                        void *ws, int32_t *F, int64_t ldF, hipStream_t stream)
 {
+    HaarPlan fp;
+    if (haar_fused_plan(I, ldI, H, W, a, b, kv, kh, neg, fp)) {
+        const dim3 grid(fp.ntx * fp.nsy);
+#define BZ_HAAR_FUSED(KV, KH)                                                                                   \
+    launch_fused<KV, KH>(fp.ndw, grid, stream, I, ldI, W, a, b, fp.Hf, fp.Wf, fp.step, fp.ntx, fp.S, fp.nsy, F, \
+                         ldF)
+        if (kv == 1 && kh == 2) BZ_HAAR_FUSED(1, 2);
+        else if (kv == 2 && kh == 1) BZ_HAAR_FUSED(2, 1);
+        else if (kv == 1 && kh == 3) BZ_HAAR_FUSED(1, 3);
+        else if (kv == 3 && kh == 1) BZ_HAAR_FUSED(3, 1);
+        else BZ_HAAR_FUSED(2, 2);
+#undef BZ_HAAR_FUSED
+        return hipGetLastError();
+    }
     const int Hv = H - a + 1, Hf = H - kv * a + 1, Wf = W - kh * b + 1;
     const int64_t ldV = haar_ld(W);
     uint16_t *V = (uint16_t *)ws;

@@ -20,6 +20,7 @@
 // The quantile is tracked incrementally: the lane keeps its current answer Q
 // and lt = #{window values < Q}, adjusts lt as values enter and leave, then
 // walks Q down or up until lt < rho <= lt + hist[Q].
+#include "device.hpp"
 #include "internal.hpp"
 
 #include <math.h>
@@ -28,18 +29,6 @@ namespace bz {
 namespace {
 
 constexpr int QLANES = 64;
-
-__device__ __forceinline__ int xcd_remap_q(int b, int n)
-{
-    const int q = n >> 3, rem = n & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
-}
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t qrsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
 
 // The bytes of one row the wave needs, [cs, cs + nb), held as aligned dwords
 // from the dword containing byte cs: lane t holds dwords t and 64 + t.
@@ -57,7 +46,7 @@ struct RowBytes {
         // whole dwords only: a dword crossing the descriptor end reads zero,
         // and the aligned dword holding the last byte is readable memory
         const uint32_t bytes = (uint32_t)((sh + nb + 3) & ~3);
-        const __amdgpu_buffer_rsrc_t d = qrsrc(ap, bytes);
+        const __amdgpu_buffer_rsrc_t d = rsrc(ap, bytes);
         d0 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane, 0, 0);
         d1 = TWO ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane + 256, 0, 0) : 0u;
     }
@@ -369,7 +358,7 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
     constexpr int NW = PACK ? 128 : 256;
     __shared__ uint32_t hist[NW * QLANES];  // [NW][QLANES] words: bin-major, lane-minor
     const int lane = threadIdx.x;
-    const int L = xcd_remap_q(blockIdx.x, gridDim.x);
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = L / nsy;
     const int sy = L - tx * nsy;
     const int x0 = tx * QLANES;
@@ -414,7 +403,7 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
     }
 
     auto pixel = [&](int y) {  // the lane's own pixel of row y (for the mask)
-        const __amdgpu_buffer_rsrc_t d = qrsrc(a.I + (int64_t)y * a.ldI + x0, (uint32_t)(W - x0));
+        const __amdgpu_buffer_rsrc_t d = rsrc(a.I + (int64_t)y * a.ldI + x0, (uint32_t)(W - x0));
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(d, lane, 0, 0);
     };
     auto finish = [&](int y, uint32_t iv) {  // walk to row y's quantile and store it

@@ -33,6 +33,7 @@
 // and the k and R gradients are sums with cancellation), then the sigmoid
 // and the gradient fields in float32.
 #include "../../include/binarize.h"
+#include "device.hpp"
 #include "internal.hpp"
 
 #include <math.h>
@@ -87,18 +88,6 @@ struct SoftArgs {
     int nt;             // tile shape: 64 (one wave) or 256 threads
     int vec;            // rows allow 16-byte loads (ld and W multiples of 4)
 };
-
-__device__ __forceinline__ int xcd_remap_s(int b, int n)
-{
-    const int q = n >> 3, rem = n & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < rem) ? x * (q + 1) + i : rem * (q + 1) + (x - rem) * q + i;
-}
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t srsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -195,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int L = xcd_remap_s(blockIdx.x, gridDim.x);
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int per_img = a.ntx * a.nsy;
     const int b = L / per_img;
     const int rem = L - b * per_img;
@@ -221,8 +210,8 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
     auto load_row = [&](int row, float v1[4], float v2[4]) {
         const bool in = row >= rlo && row <= rhi;
         const uint32_t so = in ? (uint32_t)(4 * (int64_t)(row - rlo) * pitch) : 0u;
-        ql.load(srsrc(base1, in ? span : 0u), so, v1);
-        if (PH == ADJ) ql.load(srsrc(base2, in ? span : 0u), so, v2);
+        ql.load(rsrc(base1, in ? span : 0u), so, v1);
+        if (PH == ADJ) ql.load(rsrc(base2, in ? span : 0u), so, v2);
     };
     // X1 += sign v1 and X2 += sign (v1^2 or v2), binary64 (squares exact)
     auto accumulate = [&](double X1[4], double X2[4], const float v1[4], const float v2[4], bool add) {
@@ -259,7 +248,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
     // row y: 4 y pitch); the planner keeps image spans under 2^31 bytes
     const uint32_t img_bytes = (uint32_t)(4 * ((int64_t)(H - 1) * ld + W));
     const uint32_t fld_bytes = (uint32_t)(4 * (int64_t)H * W);
-    const __amdgpu_buffer_rsrc_t dI = srsrc(a.I + (int64_t)b * H * ld, img_bytes);
+    const __amdgpu_buffer_rsrc_t dI = rsrc(a.I + (int64_t)b * H * ld, img_bytes);
 
     float kb = 0.0f, kR = 0.0f, rRf = 0.0f;
     double kb64 = 0.0, rR64 = 1.0, cR64 = 0.0;
@@ -291,8 +280,8 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
     load_row(y0 - a.eo, nl1, nl2);
     double dk_acc = 0.0, dR_acc = 0.0;
     const __amdgpu_buffer_rsrc_t dX =  // second per-pixel input of the epilogue
-        (PH == BWD1) ? srsrc(a.gy + (int64_t)b * H * ld, img_bytes)
-                     : srsrc((PH == ADJ) ? a.dd + (int64_t)b * H * W : a.I, (PH == ADJ) ? fld_bytes : 0u);
+        (PH == BWD1) ? rsrc(a.gy + (int64_t)b * H * ld, img_bytes)
+                     : rsrc((PH == ADJ) ? a.dd + (int64_t)b * H * W : a.I, (PH == ADJ) ? fld_bytes : 0u);
     // the epilogue's per-pixel inputs of a row (I, and gy or dd), loaded one
     // row ahead; row H lies past the descriptors and reads zero
     auto load_epi = [&](int y, float Iv[4], float Xv[4]) {
@@ -408,15 +397,15 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
                 typedef int v2i __attribute__((ext_vector_type(2)));
                 const v2i w1 = {__double2loint(S1), __double2hiint(S1)};
                 const v2i w2 = {__double2loint(S2), __double2hiint(S2)};
-                __builtin_amdgcn_raw_buffer_store_b64(w1, srsrc(a.S1 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
+                __builtin_amdgcn_raw_buffer_store_b64(w1, rsrc(a.S1 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
                                                       (int)so8, 0);
-                __builtin_amdgcn_raw_buffer_store_b64(w2, srsrc(a.S2 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
+                __builtin_amdgcn_raw_buffer_store_b64(w2, rsrc(a.S2 + (int64_t)b * H * a.ldS, sbytes), (int)o8,
                                                       (int)so8, 0);
                 continue;
             }
             if (PH == ADJ) {
                 const float g = Xvs[j] + (float)S1 + 2.0f * Iv * (float)S2;
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g), srsrc(a.gI + (int64_t)b * H * ld, img_bytes),
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g), rsrc(a.gI + (int64_t)b * H * ld, img_bytes),
                                                       (int)oe[j], (int)soI, 2);
                 continue;
             }
@@ -430,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
                 const float z = (Iv - t) * rtau;
                 const float ea = __expf(-fabsf(z));
                 const float yv = (z >= 0.0f ? 1.0f : ea) * __builtin_amdgcn_rcpf(1.0f + ea);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(yv), srsrc(a.y + (int64_t)b * H * ld, img_bytes),
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(yv), rsrc(a.y + (int64_t)b * H * ld, img_bytes),
                                                       (int)oe[j], (int)soI, 2);
                 continue;
             }
@@ -462,9 +451,9 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
             const float rns = s > 0.0f ? rn * __builtin_amdgcn_rcpf(s) : 0.0f;
             const float g1 = __builtin_fmaf(-beta * m, rns, aa * rn);
             const float g2 = 0.5f * beta * rns;
-            const __amdgpu_buffer_rsrc_t f1 = srsrc(a.G1 + (int64_t)b * H * W, fld_bytes);
-            const __amdgpu_buffer_rsrc_t f2 = srsrc(a.G2 + (int64_t)b * H * W, fld_bytes);
-            const __amdgpu_buffer_rsrc_t f3 = srsrc(a.dd + (int64_t)b * H * W, fld_bytes);
+            const __amdgpu_buffer_rsrc_t f1 = rsrc(a.G1 + (int64_t)b * H * W, fld_bytes);
+            const __amdgpu_buffer_rsrc_t f2 = rsrc(a.G2 + (int64_t)b * H * W, fld_bytes);
+            const __amdgpu_buffer_rsrc_t f3 = rsrc(a.dd + (int64_t)b * H * W, fld_bytes);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g1), f1, (int)oe[j], (int)soF, 0);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g2), f2, (int)oe[j], (int)soF, 0);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(delta * rtau), f3, (int)oe[j], (int)soF, 0);

@@ -1,7 +1,8 @@
 """GPU parity of the Haar-like features (bz_haar_features) against the
 oracle: exact int32 values for every template, small and ragged images, a
 strided input, 1 x 1 and 257-row cells, templates as large as the image, and
-the 3072 x 4096 page."""
+the 3072 x 4096 page, for the single-launch form (at each tile width and
+several strip heights) and the two-launch form."""
 import numpy as np
 import pytest
 import torch
@@ -66,13 +67,37 @@ def test_haar_extremes_of_the_value_range(bz):
     check(bz, I[:, ::-1].copy(), a, b, "edge_h")
 
 
-@pytest.mark.parametrize("kind", ["edge_h", "checker", "line_v"])
-def test_haar_headline_page(bz, kind):
-    check(bz, gen_document(3072, 4096, 2, noise=10.0, stain=True), 12, 12, kind)
+@pytest.mark.parametrize("kind,a", [("edge_h", 12), ("checker", 12), ("line_v", 12), ("line_v", 48)])
+def test_haar_headline_page(bz, kind, a):
+    check(bz, gen_document(3072, 4096, 2, noise=10.0, stain=True), a, a, kind)
+
+
+@pytest.mark.parametrize("kind", sorted(KINDS))
+@pytest.mark.parametrize("ndw,strip", [(1, 1), (1, 5), (2, 3), (2, 64), (1, 1000)])
+def test_haar_fused_tiles_and_strips(bz, monkeypatch, kind, ndw, strip):
+    # the single-launch form at each tile width (256 or 512 columns of G per
+    # wavefront) and strip height, on a page several tiles wide with a ragged
+    # last tile and strip, and on an aligned strided view
+    monkeypatch.setenv("BZ_HAAR_NDW", str(ndw))
+    monkeypatch.setenv("BZ_HAAR_STRIP", str(strip))
+    I = gen_document(211, 1337, 31, noise=10.0, stain=True)
+    check(bz, I, 7, 11, kind)
+    big = torch.zeros((211, 1352), dtype=torch.uint8, device="cuda")
+    big[:, 8:1345] = torch.from_numpy(I).cuda()
+    check(bz, I, 9, 29, kind, view=big[:, 8:1345])
+
+
+@pytest.mark.parametrize("kind", sorted(KINDS))
+def test_haar_two_launch_form(bz, monkeypatch, kind):
+    # BZ_HAAR_FUSED=0: the column-sum field and row kernel, on aligned rows
+    monkeypatch.setenv("BZ_HAAR_FUSED", "0")
+    check(bz, gen_document(203, 301, 77, noise=10.0, stain=True), 5, 9, kind)
 
 
 @pytest.mark.parametrize("kind,H,W,a,b", [("edge_h", 40, 17000, 5, 257), ("line_v", 70, 6000, 20, 9),
                                           ("checker", 50, 8000, 10, 77)])
-def test_haar_rows_wider_than_the_row_kernel(bz, kind, H, W, a, b):
+def test_haar_rows_wider_than_the_row_kernel(bz, monkeypatch, kind, H, W, a, b):
     # kv * W above 12288 (48 KiB of prefixes): the prefix and combine launches
+    # of the two-launch form
+    monkeypatch.setenv("BZ_HAAR_FUSED", "0")
     check(bz, gen_document(H, W, 600 + kind.__len__(), noise=10.0, stain=True), a, b, kind)

@@ -98,6 +98,25 @@ def test_feng_integer_exponent_and_constant_image(bz):
         check(bz, C, 7, 9, name)
 
 
+@pytest.mark.parametrize("gamma", [0.0, -0.5, 0.25, 2.5])
+def test_feng_powers_on_flat_and_textured_windows(bz, monkeypatch, gamma):
+    # x^g on the float32 path comes from the native log2 and exp2; flat
+    # windows (x = 0) take pow's value at 0, which for g < 0 is infinite.
+    # A noiseless page (flat background) with a noisy block: masks equal the
+    # oracle's (up to its near-ties) and the binary64 sequence's everywhere
+    I = gen_document(300, 400, 13, noise=0.0, stain=False)
+    I[100:220, 120:320] = gen_document(120, 200, 14, noise=12.0, stain=True)
+    p = (0.85, 0.15, 0.05, gamma, 96.0)
+    check(bz, I, 11, 13, "feng", params=p)
+    d = dev(I)
+    rec = bz.global_stats(d)
+    fast = bz.table1_threshold(d, 11, 13, "feng", p, stats=rec)
+    monkeypatch.setenv("BZ_FORCE_REFERENCE", "1")
+    ref = bz.table1_threshold(d, 11, 13, "feng", p, stats=rec)
+    torch.cuda.synchronize()
+    assert torch.equal(fast[0], ref[0])
+
+
 def test_global_record_is_reused(bz):
     # a record computed once serves several calls; outputs equal the
     # call that computes its own record
