@@ -1,16 +1,20 @@
 // Windowed quantiles from sliding 256-bin gray-level histograms (Section 3.4).
 //
-// A workgroup is one wavefront; lane t owns output column x0 + t and slides
-// its window histogram DOWN a strip of rows: per row it adds the w gray
-// levels of the entering row and removes those of the leaving row (the
+// Each wavefront works on its own tile; lane t owns output column x0 + t and
+// slides its window histogram DOWN a strip of rows: per row it adds the w
+// gray levels of the entering row and removes those of the leaving row (the
 // Theta(max{h,w}) per-pixel cost the paper states).
 //
-// Histograms are private per lane and live in LDS with the bin as the major
-// dimension, so each lane always hits its own bank.  When no count can
-// exceed 65535 (h w <= 65535) two adjacent bins share a 32-bit word (bin v
-// in half v & 1 of word v >> 1: 32 KB per wave, four waves per CU);
-// otherwise each bin has a word (64 KB per wave).  Bin updates are
-// fire-and-forget LDS atomics.
+// Histograms are private per lane and live in a 64 KB LDS array of 256 bin
+// rows of 64 words, the bin as the major dimension: a lane's bin v is in row
+// v at its slot, so each lane always hits its own bank.  When no count can
+// exceed 65535 (h w <= 65535) the bins are 16 bits and two lanes share a
+// slot: a workgroup holds two wavefronts, lane t of wave u has slot
+// 32 u + (t mod 32) and the half t / 32 of it (four waves per CU); otherwise a
+// workgroup is one wavefront and lane t has all of slot t (two per CU).  A
+// bin's byte offset, 256 v + 4 slot, is then one byte permute of the gray
+// level and the slot, and its increment (1 or 65536) a constant of the lane.
+// Bin updates are fire-and-forget LDS atomics.
 //
 // Row data: the wave loads the bytes its 64 windows need from a row (at most
 // 64 + w - 1 of them) as aligned dwords, one or two per lane, prefetched a
@@ -24,6 +28,7 @@
 #include "internal.hpp"
 
 #include <math.h>
+#include <stdlib.h>
 
 namespace bz {
 namespace {
@@ -61,32 +66,28 @@ struct RowBytes {
     }
 };
 
+// A lane's place in the histogram array: its slot's byte offset in a bin row
+// (s4 = 4 slot, at most 252), the increment of one count (1, or 65536 for the
+// high half of a shared slot) and the shift of its half.
+struct Slot {
+    uint32_t s4, inc, sh;
+};
+
+// The count of a bin from its word.
 template <bool PACK>
-__device__ __forceinline__ uint32_t bin_word(uint32_t v) { return PACK ? (v >> 1) : v; }
-template <bool PACK>
-__device__ __forceinline__ uint32_t bin_inc(uint32_t v) { return PACK ? ((v & 1u) ? 65536u : 1u) : 1u; }
-template <bool PACK>
-__device__ __forceinline__ int bin_count(const uint32_t *hb, int g)
+__device__ __forceinline__ int bin_of(uint32_t wd, const Slot &slot)
 {
-    const uint32_t wd = hb[(uint32_t)bin_word<PACK>((uint32_t)g) * QLANES];
-    return PACK ? (int)((wd >> ((g & 1) * 16)) & 0xffffu) : (int)wd;
+    return PACK ? (int)((wd >> slot.sh) & 0xffffu) : (int)wd;
 }
 
-// LDS word of byte q of val in the lane's histogram, as a byte offset from
-// the histogram base (lane4 = 4 lane), and the signed increment of its bin:
-// +-(1 + 65535 b) adds one to the low (b = 0) or high half of a packed word
-// (one 24-bit multiply-add).
-template <bool PACK, int q, int SIGN>
-__device__ __forceinline__ void bin_slot(uint32_t val, uint32_t lane4, uint32_t &off, uint32_t &inc)
+// Byte offset of the bin of byte q of val in the lane's histogram,
+// 256 byte + s4 (one permute: byte 0 from s4, byte 1 from val), and the
+// signed increment of its count.
+template <int q, int SIGN>
+__device__ __forceinline__ void bin_slot(uint32_t val, const Slot &slot, uint32_t &off, uint32_t &inc)
 {
-    if (PACK) {
-        off = (((val >> (8 * q + 1)) & 0x7fu) << 8) | lane4;  // word v >> 1 at (v >> 1) * 256 + lane4
-        const int b = (int)((val >> (8 * q)) & 1u);
-        inc = (uint32_t)(__mul24(b, SIGN * 65535) + SIGN);
-    } else {
-        off = (((val >> (8 * q)) & 0xffu) << 8) | lane4;  // word v at v * 256 + lane4
-        inc = (uint32_t)SIGN;
-    }
+    off = __builtin_amdgcn_perm(slot.s4, val, 0x0c0c0004u | ((uint32_t)q << 8));
+    inc = SIGN > 0 ? slot.inc : 0u - slot.inc;
 }
 
 // Adds inc (already signed) to the word at byte offset off.
@@ -109,18 +110,18 @@ constexpr int GROUP = 8;  // dwords of row bytes per group (32 window columns)
 
 // Byte q of the entering (ve) and leaving (vl) dwords at window column c0 + q.
 template <bool PACK, bool FULL, bool BOTH, int q>
-__device__ __forceinline__ void group_bytes(uint32_t *hist, uint32_t lane4, uint32_t ve, uint32_t vl, bool has_e,
+__device__ __forceinline__ void group_bytes(uint32_t *hist, const Slot &slot, uint32_t ve, uint32_t vl, bool has_e,
                                             bool has_l, int c0, int wmax, int nc, int Q, int &lt)
 {
     const int c = c0 + q;
     const bool ok = FULL || (c < wmax && c < nc);
     uint32_t off, inc;
-    bin_slot<PACK, q, 1>(ve, lane4, off, inc);
+    bin_slot<q, 1>(ve, slot, off, inc);
     const bool oke = FULL || (ok && has_e);
     lds_add(hist, off, oke ? inc : 0u);
     if (BOTH) {
         const bool okl = FULL || (ok && has_l);
-        bin_slot<PACK, q, -1>(vl, lane4, off, inc);
+        bin_slot<q, -1>(vl, slot, off, inc);
         lds_add(hist, off, okl ? inc : 0u);
         if (!FULL) {
             const uint32_t v_e = (ve >> (8 * q)) & 0xffu, v_l = (vl >> (8 * q)) & 0xffu;
@@ -137,7 +138,7 @@ __device__ __forceinline__ void group_bytes(uint32_t *hist, uint32_t lane4, uint
 // zero) and compared.  BOTH false: only e is added, to the first window,
 // built with Q = 0 (no value lies below it).
 template <bool PACK, bool FULL, bool BOTH>
-__device__ __forceinline__ void group_update(uint32_t *hist, uint32_t lane4, const uint32_t *de, const uint32_t *dl,
+__device__ __forceinline__ void group_update(uint32_t *hist, const Slot &slot, const uint32_t *de, const uint32_t *dl,
                                              int se, int sl, bool has_e, bool has_l, int kbase, int wmax, int nc,
                                              int Q, int &lt)
 {
@@ -151,10 +152,10 @@ __device__ __forceinline__ void group_update(uint32_t *hist, uint32_t lane4, con
             ge_e += ge_fields(ve, K);
             ge_l += ge_fields(vl, K);
         }
-        group_bytes<PACK, FULL, BOTH, 0>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 1>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 2>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 3>(hist, lane4, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 0>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 1>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 2>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, 3>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
     }
     if (FULL && BOTH) {
         // bytes below Q: entering minus leaving = (32 - ge_e) - (32 - ge_l)
@@ -169,7 +170,7 @@ __device__ __forceinline__ void group_update(uint32_t *hist, uint32_t lane4, con
 // per group, not per dword.  clip: some lane's window is clipped by the
 // image border (nc < w).  BOTH false: only e is added (the first window).
 template <bool PACK, bool TWO, bool BOTH>
-__device__ __forceinline__ void slide_rows(uint32_t *hist, uint32_t lane4, const RowBytes<TWO> &e, const RowBytes<TWO> &l, bool has_e,
+__device__ __forceinline__ void slide_rows(uint32_t *hist, const Slot &slot, const RowBytes<TWO> &e, const RowBytes<TWO> &l, bool has_e,
                                            bool has_l, int rel, int nc, int wmax, bool clip, int Q, int &lt)
 {
     const int be = e.sh + rel, bl = l.sh + rel;
@@ -186,73 +187,58 @@ __device__ __forceinline__ void slide_rows(uint32_t *hist, uint32_t lane4, const
             dl[t] = BOTH ? l.dword(il + k / 4 + t) : 0u;
         }
         if (fast && k + 4 * GROUP <= wmax)
-            group_update<PACK, true, BOTH>(hist, lane4, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+            group_update<PACK, true, BOTH>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
         else
-            group_update<PACK, false, BOTH>(hist, lane4, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+            group_update<PACK, false, BOTH>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
     }
 }
 
 // Walk Q to the rho-th smallest window value: down while lt >= rho, up while
-// lt + hist[Q] < rho (Q stays in [0, 255] whatever the counts hold).  Each
-// LDS round trip reads WALK_WORDS words (16 bins when packed), issued
-// together; a quantile that jumps across an edge then costs a few round
-// trips instead of one per bin.
+// lt + hist[Q] < rho (Q stays in [0, 255] whatever the counts hold).  The
+// common case, Q unchanged, costs one LDS read; otherwise each round trip
+// reads WALK_WORDS bins, issued together, so that a quantile that jumps
+// across an edge costs a few round trips instead of one per bin.  hb: the
+// lane's slot in bin row 0.
 constexpr int WALK_WORDS = 8;
 template <bool PACK>
-__device__ __forceinline__ void walk(const uint32_t *hb, int rho, int &Q, int &lt)
+__device__ __forceinline__ void walk(const uint32_t *hb, const Slot &slot, int rho, int &Q, int &lt)
 {
-    constexpr int BPW = PACK ? 2 : 1;  // bins per word
-    constexpr int NWORDS = 256 / BPW;
+    if (lt < rho && (Q >= 255 || lt + bin_of<PACK>(hb[Q * QLANES], slot) >= rho)) return;
     // each step below is a select, so the lanes of a chunk stay converged
     while (lt >= rho && Q > 0) {
-        // the word of bin Q-1 and the WALK_WORDS-1 words below it
-        const int w0 = (Q - 1) / BPW;
-        const int lowest = (w0 - WALK_WORDS + 1 > 0 ? w0 - WALK_WORDS + 1 : 0) * BPW;
-        // WALK_WORDS consecutive words from `base` (a multiple-of-64-word
-        // stride apart, read in pairs), covering the word of Q-1 and those
-        // below it; words above Q-1's are read but not stepped to
-        const int base = lowest / BPW;
+        // bins Q-1 and the WALK_WORDS-1 below it (from 0 at the bottom)
+        const int base = Q - WALK_WORDS > 0 ? Q - WALK_WORDS : 0;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) wd[t] = hb[(base + t) * QLANES];
 #pragma unroll
         for (int t = WALK_WORDS - 1; t >= 0; --t) {
-#pragma unroll
-            for (int hi = BPW - 1; hi >= 0; --hi) {
-                const int g = (base + t) * BPW + hi;
-                const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
-                const bool step = g == Q - 1 && g >= lowest && lt >= rho;
-                lt = step ? lt - cnt : lt;
-                Q = step ? g : Q;
-            }
+            const int g = base + t;
+            const bool step = g == Q - 1 && lt >= rho;
+            lt = step ? lt - bin_of<PACK>(wd[t], slot) : lt;
+            Q = step ? g : Q;
         }
     }
     bool found = Q >= 255;
     while (!found) {
-        // the word of bin Q and the WALK_WORDS-1 words above it
-        const int w0 = Q / BPW;
-        // WALK_WORDS consecutive words from `base`, covering Q's word and
-        // those above it (base < w0 only at the top, where bins below Q are
-        // skipped and the walk stops at bin 255)
-        const int base = w0 < NWORDS - WALK_WORDS ? w0 : NWORDS - WALK_WORDS;
+        // bin Q and the WALK_WORDS-1 above it (base < Q only at the top,
+        // where bins below Q are skipped and the walk stops at bin 255)
+        const int base = Q < 256 - WALK_WORDS ? Q : 256 - WALK_WORDS;
         uint32_t wd[WALK_WORDS];
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) wd[t] = hb[(base + t) * QLANES];
         const int q0 = Q;
 #pragma unroll
         for (int t = 0; t < WALK_WORDS; ++t) {
-#pragma unroll
-            for (int hi = 0; hi < BPW; ++hi) {
-                const int g = (base + t) * BPW + hi;
-                const int cnt = PACK ? (int)((wd[t] >> (16 * hi)) & 0xffffu) : (int)wd[t];
-                const bool live = !found && g >= q0;
-                const bool hit = live && (g >= 255 || lt + cnt >= rho);
-                lt = (live && !hit) ? lt + cnt : lt;
-                Q = hit ? g : Q;
-                found = found || hit;
-            }
+            const int g = base + t;
+            const int cnt = bin_of<PACK>(wd[t], slot);
+            const bool live = !found && g >= q0;
+            const bool hit = live && (g >= 255 || lt + cnt >= rho);
+            lt = (live && !hit) ? lt + cnt : lt;
+            Q = hit ? g : Q;
+            found = found || hit;
         }
-        Q = found ? Q : (base + WALK_WORDS) * BPW;
+        Q = found ? Q : base + WALK_WORDS;
     }
 }
 
@@ -265,6 +251,7 @@ constexpr int PGROUP = 8;
 struct PipeRow {
     uint32_t off[2][4 * PGROUP], inc[2][4 * PGROUP];  // [entering, leaving] updates
     uint32_t raw[2][PGROUP];                          // their bytes (255 where not counted)
+    bool full;  // every update counts: inc unused, the lane's constant increments apply
 };
 
 // The row span dwords of a lane's window bytes: GROUP + 1 per row; se, sl:
@@ -285,15 +272,15 @@ __device__ __forceinline__ void fetch_rows(uint32_t *de, uint32_t *dl, int &se, 
 
 template <bool PACK, bool FULL, int q>
 __device__ __forceinline__ void decode_byte(PipeRow &S, int t, uint32_t ve, uint32_t vl, uint32_t me, uint32_t ml,
-                                            uint32_t lane4)
+                                            const Slot &slot)
 {
     uint32_t off, inc;
-    bin_slot<PACK, q, 1>(ve, lane4, off, inc);
+    bin_slot<q, 1>(ve, slot, off, inc);
     S.off[0][4 * t + q] = off;
-    S.inc[0][4 * t + q] = (FULL || ((me >> (8 * q)) & 1u) == 0u) ? inc : 0u;
-    bin_slot<PACK, q, -1>(vl, lane4, off, inc);
+    if (!FULL) S.inc[0][4 * t + q] = ((me >> (8 * q)) & 1u) == 0u ? inc : 0u;
+    bin_slot<q, -1>(vl, slot, off, inc);
     S.off[1][4 * t + q] = off;
-    S.inc[1][4 * t + q] = (FULL || ((ml >> (8 * q)) & 1u) == 0u) ? inc : 0u;
+    if (!FULL) S.inc[1][4 * t + q] = ((ml >> (8 * q)) & 1u) == 0u ? inc : 0u;
 }
 
 // Offsets and increments of a row's updates.  FULL: all 4 PGROUP columns are
@@ -302,8 +289,9 @@ __device__ __forceinline__ void decode_byte(PipeRow &S, int t, uint32_t ve, uint
 // which no rank count takes as below Q.
 template <bool PACK, bool FULL>
 __device__ __forceinline__ void decode_rows(PipeRow &S, const uint32_t *de, const uint32_t *dl, int se, int sl,
-                                            bool has_e, bool has_l, int wmax, int nc, uint32_t lane4)
+                                            bool has_e, bool has_l, int wmax, int nc, const Slot &slot)
 {
+    S.full = FULL;
 #pragma unroll
     for (int t = 0; t < PGROUP; ++t) {
         uint32_t ve = __builtin_amdgcn_alignbyte(de[t + 1], de[t], se);
@@ -322,19 +310,28 @@ __device__ __forceinline__ void decode_rows(PipeRow &S, const uint32_t *de, cons
         }
         S.raw[0][t] = ve;
         S.raw[1][t] = vl;
-        decode_byte<PACK, FULL, 0>(S, t, ve, vl, me, ml, lane4);
-        decode_byte<PACK, FULL, 1>(S, t, ve, vl, me, ml, lane4);
-        decode_byte<PACK, FULL, 2>(S, t, ve, vl, me, ml, lane4);
-        decode_byte<PACK, FULL, 3>(S, t, ve, vl, me, ml, lane4);
+        decode_byte<PACK, FULL, 0>(S, t, ve, vl, me, ml, slot);
+        decode_byte<PACK, FULL, 1>(S, t, ve, vl, me, ml, slot);
+        decode_byte<PACK, FULL, 2>(S, t, ve, vl, me, ml, slot);
+        decode_byte<PACK, FULL, 3>(S, t, ve, vl, me, ml, slot);
     }
 }
 
-__device__ __forceinline__ void apply_rows(uint32_t *hist, const PipeRow &S)
+__device__ __forceinline__ void apply_rows(uint32_t *hist, const PipeRow &S, const Slot &slot)
 {
+    if (S.full) {
+        const uint32_t ie = slot.inc, il = 0u - slot.inc;
 #pragma unroll
-    for (int i = 0; i < 4 * PGROUP; ++i) {
-        lds_add(hist, S.off[0][i], S.inc[0][i]);
-        lds_add(hist, S.off[1][i], S.inc[1][i]);
+        for (int i = 0; i < 4 * PGROUP; ++i) {
+            lds_add(hist, S.off[0][i], ie);
+            lds_add(hist, S.off[1][i], il);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4 * PGROUP; ++i) {
+            lds_add(hist, S.off[0][i], S.inc[0][i]);
+            lds_add(hist, S.off[1][i], S.inc[1][i]);
+        }
     }
 }
 
@@ -352,13 +349,20 @@ __device__ __forceinline__ void count_below(const PipeRow &S, int Q, int &lt)
     lt += (int)(((ge_l >> 8) & 0xffu) + (ge_l >> 24)) - (int)(((ge_e >> 8) & 0xffu) + (ge_e >> 24));
 }
 
+// Wavefronts of a workgroup: two sharing the slots of 16-bit bins, or one.
+template <bool PACK>
+constexpr int qwaves() { return PACK ? 2 : 1; }
+
+// Workgroup b: wavefront u works on tile qwaves() * b + u (in XCD order) of
+// the ntiles = ntx * nsy tiles, with no barrier between the wavefronts.
 template <bool PACK, bool TWO>
-__global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int nsy)
+__global__ __launch_bounds__(qwaves<PACK>() * QLANES) void k_quantile(QuantJob a, int seg, int nsy, int ntiles)
 {
-    constexpr int NW = PACK ? 128 : 256;
-    __shared__ uint32_t hist[NW * QLANES];  // [NW][QLANES] words: bin-major, lane-minor
-    const int lane = threadIdx.x;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    __shared__ uint32_t hist[256 * QLANES];  // 256 bin rows of 64 slots (64 KB)
+    const int lane = threadIdx.x & (QLANES - 1);
+    const int u = PACK ? (int)(threadIdx.x >> 6) : 0;
+    const int L = qwaves<PACK>() * xcd_remap(blockIdx.x, gridDim.x) + u;
+    if (L >= ntiles) return;  // the second wavefront of the last workgroup
     const int tx = L / nsy;
     const int sy = L - tx * nsy;
     const int x0 = tx * QLANES;
@@ -368,10 +372,18 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
     const int y1 = min(y0 + seg, a.H);
     const int H = a.H, W = a.W;
 
-    uint32_t *hb = hist + lane;
-    const uint32_t lane4 = 4u * (uint32_t)lane;
+    const uint32_t sidx = PACK ? 32u * (uint32_t)u + (uint32_t)(lane & 31) : (uint32_t)lane;
+    Slot slot;
+    slot.s4 = 4u * sidx;
+    slot.inc = (PACK && lane >= 32) ? 65536u : 1u;
+    slot.sh = (PACK && lane >= 32) ? 16u : 0u;
+    uint32_t *hb = hist + sidx;
+    // clear the lane's bins (a shared slot by its low-half lane, before any
+    // update: one wavefront's LDS operations take effect in order)
+    if (!PACK || lane < 32) {
 #pragma unroll 8
-    for (int b = 0; b < NW; ++b) hb[b * QLANES] = 0u;
+        for (int b = 0; b < 256; ++b) hb[b * QLANES] = 0u;
+    }
 
     // bytes any lane of the wave needs: columns cs .. ce
     const int cs = max(x0 - a.l + 1, 0);
@@ -398,7 +410,7 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
         for (int row = r0; row <= r1; ++row) {
             RowBytes<TWO> cur = rb;
             if (row < r1) rb.load(rowp(row + 1), nb, lane);
-            slide_rows<PACK, TWO, false>(hist, lane4, cur, cur, true, false, rel, nc, wmax, clip, Q, lt);
+            slide_rows<PACK, TWO, false>(hist, slot, cur, cur, true, false, rel, nc, wmax, clip, Q, lt);
         }
     }
 
@@ -412,7 +424,7 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
         const int n = nr * nc;  // at most 257 * 257
         int rho = (int)ceil(a.q * (double)n);
         if (rho < 1) rho = 1;
-        walk<PACK>(hb, rho, Q, lt);
+        walk<PACK>(hb, slot, rho, Q, lt);
         a.Q[(int64_t)y * a.ldQ + j] = (uint8_t)Q;
         if (a.mask) a.mask[(int64_t)y * a.ldM + j] = (iv < (uint32_t)Q) ? 1 : 0;
     };
@@ -443,14 +455,14 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
             if (yn < y1) {
                 int se, sl;
                 fetch_rows(de, dl, se, sl, eA, lA, rel);  // before this row's atomics
-                if (y > y0) apply_rows(hist, S);
+                if (y > y0) apply_rows(hist, S, slot);
                 const bool has_e = yn + a.u < H, has_l = yn - a.o >= 0;
                 if (has_e && has_l && !clip && wmax == 4 * PGROUP)
-                    decode_rows<PACK, true>(S, de, dl, se, sl, has_e, has_l, wmax, nc, lane4);
+                    decode_rows<PACK, true>(S, de, dl, se, sl, has_e, has_l, wmax, nc, slot);
                 else
-                    decode_rows<PACK, false>(S, de, dl, se, sl, has_e, has_l, wmax, nc, lane4);
+                    decode_rows<PACK, false>(S, de, dl, se, sl, has_e, has_l, wmax, nc, slot);
             } else if (y > y0) {
-                apply_rows(hist, S);
+                apply_rows(hist, S, slot);
             }
             const uint32_t iv = px;
             // advance the load pipeline: A <- B, B <- row y + 3
@@ -485,24 +497,26 @@ __global__ __launch_bounds__(QLANES) void k_quantile(QuantJob a, int seg, int ns
         if (y + 1 < y1) load_row(y + 1);
         if (y > y0) {
             const bool has_e = y + a.u < H, has_l = y - a.o >= 0;
-            slide_rows<PACK, TWO, true>(hist, lane4, e, l, has_e, has_l, rel, nc, wmax, clip, Q, lt);
+            slide_rows<PACK, TWO, true>(hist, slot, e, l, has_e, has_l, rel, nc, wmax, clip, Q, lt);
         }
         finish(y, iv);
     }
 }
 
 template <bool PACK, bool TWO>
-void launch_variant(const QuantJob &a, int blocks, int seg, int nsy, hipStream_t stream)
+void launch_variant(const QuantJob &a, int ntiles, int seg, int nsy, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_quantile<PACK, TWO>), dim3(blocks), dim3(QLANES), 0, stream, a, seg, nsy);
+    constexpr int nw = qwaves<PACK>();
+    hipLaunchKernelGGL((k_quantile<PACK, TWO>), dim3((ntiles + nw - 1) / nw), dim3(nw * QLANES), 0, stream, a, seg,
+                       nsy, ntiles);
 }
 
 }  // namespace
 
-// Waves of histogram size `lds` bytes that stay resident on the device at
+// Workgroups of `lds` bytes of LDS that stay resident on the device at
 // once.  Measured on MI355X: four 32 KB workgroups fit on a CU but not five
 // (five fit at 31 KB), so the usable LDS per CU is taken as 158 KB.
-static int resident_waves(size_t lds)
+static int resident_groups(size_t lds)
 {
     int device = 0, cus = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
@@ -519,22 +533,24 @@ hipError_t launch_quantile(const QuantJob &a, hipStream_t stream)
     // strips: one resident round of waves (a wave more would run in a
     // second round), and at least h/2 rows (building the first window
     // costs h w updates against 2 w per row of the slide)
-    const long target = resident_waves((pack ? 128 : 256) * QLANES * sizeof(uint32_t));
+    const long target = (long)resident_groups(256 * QLANES * sizeof(uint32_t)) * (pack ? 2 : 1);
     int seg = (int)(((long)a.H * ntx + target - 1) / target);
     if (seg < (a.h + 1) / 2) seg = (a.h + 1) / 2;
     if (seg < 8) seg = 8;
+    const char *e = getenv("BZ_QUANTILE_STRIP");  // tuning override
+    if (e && atoi(e) > 0) seg = atoi(e);
     if (seg > a.H) seg = a.H;
     const int nsy = (a.H + seg - 1) / seg;
     // dwords a lane reads from the row span: from (sh + rel) / 4 <= 16 to
     // 16 + (w - 1) / 4 + 1; one dword per lane holds dwords 0 .. 63
     const bool two = 16 + (a.w - 1) / 4 + 1 >= QLANES;
-    const int blocks = ntx * nsy;
+    const int ntiles = ntx * nsy;
     if (pack) {
-        if (two) launch_variant<true, true>(a, blocks, seg, nsy, stream);
-        else launch_variant<true, false>(a, blocks, seg, nsy, stream);
+        if (two) launch_variant<true, true>(a, ntiles, seg, nsy, stream);
+        else launch_variant<true, false>(a, ntiles, seg, nsy, stream);
     } else {
-        if (two) launch_variant<false, true>(a, blocks, seg, nsy, stream);
-        else launch_variant<false, false>(a, blocks, seg, nsy, stream);
+        if (two) launch_variant<false, true>(a, ntiles, seg, nsy, stream);
+        else launch_variant<false, false>(a, ntiles, seg, nsy, stream);
     }
     return hipGetLastError();
 }
