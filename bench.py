@@ -159,22 +159,47 @@ def _loop_us(fn, n, warm=3):
     return a.elapsed_time(b) * 1e3 / n
 
 
-def ragged_batch_inputs(dev):
-    """The 256-page ragged batch: crops (at seeded offsets) of one generated
-    4096 x 4096 page, each copied into its own tensor, with the shapes and
-    parameters of the batch recipe.  Returns (images, params)."""
-    import torch
-    from docgen import batch_specs, gen_document
+def ragged_batch_pages(workers: int = 8):
+    """The 256 pages of the ragged-batch recipe (docgen.batch_specs), each
+    generated from its own seed (docgen.gen_batch), and their parameters.
+
+    The pages (1.16 Gpx) are kept in one file under the temp directory, keyed
+    by the recipe, so that a later run maps them instead of generating them
+    again: counter runs start after the profiler has initialised the GPU and
+    so must not start worker processes (they pass workers=1)."""
+    import tempfile
+    from docgen import batch_specs, gen_batch
     specs = batch_specs()
-    big = torch.from_numpy(gen_document(4096, 4096, 4, noise=10.0, stain=True)).to(dev)
-    rng = np.random.default_rng(4)
-    imgs, params = [], []
-    for d in specs:
-        y = int(rng.integers(0, 4096 - d["H"] + 1))
-        x = int(rng.integers(0, 4096 - d["W"] + 1))
-        imgs.append(big[y:y + d["H"], x:x + d["W"]].clone())
-        params.append({"h": d["h"], "w": d["w"], "k": d["k"], "R": d["R"], "method": "sauvola"})
-    return imgs, params
+    key = hashlib.sha256(json.dumps(specs, sort_keys=True).encode()).hexdigest()[:16]
+    path = os.path.join(tempfile.gettempdir(), "bz_ragged_batch_%s.npy" % key)
+    sizes = [d["H"] * d["W"] for d in specs]
+    flat = None
+    if os.path.exists(path):
+        flat = np.load(path, mmap_mode="r")
+        if flat.dtype != np.uint8 or flat.size != sum(sizes):
+            flat = None
+    if flat is None:
+        pages = gen_batch(specs, workers=workers)
+        flat = np.concatenate([p.ravel() for p in pages])
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "wb") as f:
+            np.save(f, flat)
+        os.replace(tmp, path)
+    pages, at = [], 0
+    for d, n in zip(specs, sizes):
+        pages.append(np.asarray(flat[at:at + n]).reshape(d["H"], d["W"]))
+        at += n
+    params = [{"h": d["h"], "w": d["w"], "k": d["k"], "R": d["R"], "method": "sauvola"} for d in specs]
+    return pages, params
+
+
+def ragged_batch_inputs(dev, pages=None):
+    """The ragged batch on the device: (images, params), one tensor per page."""
+    import torch
+    if pages is None:
+        pages = ragged_batch_pages(workers=1)
+    host, params = pages
+    return [torch.from_numpy(np.ascontiguousarray(p)).to(dev) for p in host], params
 
 
 def soft_workload(dev, B=32, Hs=1024, Ws=1024, win=32, tau=2.0):
@@ -213,7 +238,7 @@ def soft_workload(dev, B=32, Hs=1024, Ws=1024, win=32, tau=2.0):
     return fwd, bwd, nb
 
 
-def extras(sets, host, args):
+def extras(sets, host, args, batch_pages=None):
     """The other measured workloads: window sweep, Niblack, mask-only,
     mean/std, cache-warm, ragged batch, soft fwd+bwd, quantiles, Table 1,
     host-memory streaming."""
@@ -311,11 +336,15 @@ def extras(sets, host, args):
                 "note": "torch fill_ of 9 B/px (the output bytes of one page), rotated over 4 buffers"}
 
     def batch():
-        # 256 ragged pages: crops (at seeded offsets) of one generated 4096 x 4096
-        # page, each copied into its own tensor
-        imgs, params = ragged_batch_inputs(sets[0][0].device)
+        # the 256 ragged pages, each generated from its own seed; the timed
+        # plan takes its strip heights from the autotuner's table (measured on
+        # this device, or read from its cache)
+        from paper_1905_13038_amd import tune
+        imgs, params = ragged_batch_inputs(sets[0][0].device, batch_pages)
         tot = sum(int(t.numel()) for t in imgs)
-        plan = bz.BatchPlan(imgs, params)
+        table = tune.autotune()
+        strips = tune.strips_for(params, table)
+        plan = bz.BatchPlan(imgs, params, strips=strips)
         outs = plan.outputs()
 
         def plain(i):
@@ -330,14 +359,19 @@ def extras(sets, host, args):
         run_us = _loop_us(lambda i: plan.run(), 10, warm=2)
         plan.capture()
         graph_us = _loop_us(lambda i: plan.replay(), 10, warm=2)
+        plan_d = bz.BatchPlan(imgs, params)
+        default_us = _loop_us(lambda i: plan_d.run(), 10, warm=2)
+        del plan_d
         return {"images": len(imgs), "Gpx": round(tot / 1e9, 4),
                 "graph_replay_us": round(graph_us, 1), "persistent_run_us": round(run_us, 1),
+                "persistent_run_default_strips_us": round(default_us, 1),
                 "plain_calls_us": round(plain_us, 1),
                 "graph_Gpix_s": round(tot / graph_us / 1e3, 1),
                 "plain_Gpix_s": round(tot / plain_us / 1e3, 1),
                 "graph_hbm_frac": round(10.0 * tot / graph_us / 1e3 / HBM_PEAK_GBS, 4),
-                "inputs": "crops of one seeded 4096x4096 page at seeded offsets, shapes and "
-                          "parameters of the ragged-batch recipe (seed 4)"}
+                "strip_table": {str(c): s_ for c, s_ in sorted(table.items())},
+                "inputs": "the 256 pages of the ragged-batch recipe, each generated from its own seed "
+                          "(4000 + b), with the recipe's shapes, windows and k"}
 
     def soft():
         B, Hs, Ws, win, tau = 32, 1024, 1024, 32, 2.0
@@ -486,6 +520,19 @@ def extras(sets, host, args):
                                          "hbm_frac": round(5.0 * Hf * Wf / us / 1e3 / HBM_PEAK_GBS, 4)}
         return res
 
+    def tiling():
+        # the autotuner's single-image table (measured here), and the headline
+        # call with it installed against the built-in plan
+        from paper_1905_13038_amd import tune
+        rows = tune.autotune_plain(cache_path=None)
+        base = _loop_us(lambda i: page_call("sauvola", 75, True, i), 20)
+        bz.set_tile_table(rows)
+        try:
+            tuned = _loop_us(lambda i: page_call("sauvola", 75, True, i), 20)
+        finally:
+            bz.set_tile_table([])
+        return {"rows": rows, "headline_builtin_us": round(base, 2), "headline_tuned_us": round(tuned, 2)}
+
     guarded("window_sweep", sweep)
     guarded("sauvola_w75_mask_only", mask_only)
     guarded("sauvola_w75_transposed_3072x4096", transposed)
@@ -497,6 +544,7 @@ def extras(sets, host, args):
     guarded("quantile_2048x1536", quantiles)
     guarded("table1_4096x3072_w75", table1)
     guarded("haar_4096x3072", haar)
+    guarded("tiling_autotune_plain", tiling)
     guarded("streamed_host", streamed)
     return out
 
@@ -527,6 +575,15 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    # the ragged batch's pages are generated first, in worker processes,
+    # before anything touches the GPU
+    only = None if args.extras_only is None else set(args.extras_only.split(","))
+    batch_pages = None
+    if args.pmc and args.pmc_workload == "batch":
+        batch_pages = ragged_batch_pages(workers=1)
+    elif not args.pmc and not args.no_extras and (only is None or "ragged_batch_256" in only):
+        batch_pages = ragged_batch_pages()
+
     import torch
     import paper_1905_13038_amd as bz
     from docgen import gen_document
@@ -550,8 +607,9 @@ def main():
 
     if args.pmc:
         if args.pmc_workload == "batch":
-            imgs, params = ragged_batch_inputs(dev)
-            plan = bz.BatchPlan(imgs, params)
+            from paper_1905_13038_amd import tune
+            imgs, params = ragged_batch_inputs(dev, batch_pages)
+            plan = bz.BatchPlan(imgs, params, strips=tune.strips_for(params, tune.autotune()))
             for i in range(3):
                 plan.run()
         elif args.pmc_workload == "soft":
@@ -637,7 +695,7 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, win, win, k, R, args.cpu_seconds)
     if not args.no_extras:
-        out["extras"] = extras(sets, host, args)
+        out["extras"] = extras(sets, host, args, batch_pages)
     print(json.dumps(out), flush=True)
 
 

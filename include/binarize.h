@@ -309,6 +309,25 @@ bz_status bz_binarize_streamed(const uint8_t *I, int H, int W, ptrdiff_t ld_I, i
                                void *workspace, size_t ws_bytes, bz_stream stream,
                                bz_stream load_stream, bz_stream store_stream);
 
+/*
+ * Tiling of the single-image box-statistics calls (bz_sauvola, bz_niblack,
+ * bz_window_mean_std, bz_window_sums, bz_threshold and the bands of
+ * bz_binarize_streamed), for example from a table measured by an autotuner:
+ * `rows` is a HOST array of `count` rows of four ints (largest h, largest W,
+ * strip rows, threads per workgroup), copied during the call.  A call takes
+ * the first row, in order of (largest h, largest W), whose class holds its
+ * window height and image width; calls outside every class, or with
+ * BZ_TILE_S or BZ_TILE_THREADS set in the environment (which win), keep the
+ * built-in plan; a strip or threads of 0 in a row keeps the built-in choice
+ * of that parameter.  Results do not depend on the tiling.  count = 0 removes
+ * the table.  threads must be 0 or a multiple of 64 in [64, 1024], strip
+ * non-negative and the class bounds positive, else BZ_ERR_INVALID and the
+ * table is left unchanged.  The
+ * table is process-wide; installing it while other threads make calls is
+ * safe (each call reads it once).
+ */
+bz_status bz_set_tile_table(const int *rows, int count);
+
 /* Workspace bytes that bz_sauvola_batched needs for `count` items. */
 size_t bz_batched_workspace_size(int count);
 

@@ -22,7 +22,7 @@ __all__ = [
     "lib", "BZError", "window_sums", "window_mean_std", "sauvola", "niblack",
     "window_quantile", "sauvola_batched", "BatchPlan", "soft_sauvola", "SoftSauvola", "soft_window_sums",
     "global_stats", "read_global_stats", "table1_threshold", "TABLE1", "window_minmax", "bernsen",
-    "binarize_streamed", "haar_features", "HAAR", "LIB_PATH",
+    "binarize_streamed", "haar_features", "HAAR", "LIB_PATH", "set_tile_table",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbinarize.so")
@@ -86,6 +86,8 @@ lib.bz_haar_workspace_size.restype = _SZ
 lib.bz_haar_workspace_size.argtypes = [_I, _I, _I, _I]
 lib.bz_haar_features.restype = _I
 lib.bz_haar_features.argtypes = [_P, _I, _I, _PD, _I, _I, _I, _P, _PD, _P, _SZ, _P]
+lib.bz_set_tile_table.restype = _I
+lib.bz_set_tile_table.argtypes = [ctypes.POINTER(_I), _I]
 lib.bz_batched_workspace_size.restype = _SZ
 lib.bz_batched_workspace_size.argtypes = [_I]
 lib.bz_batched_plan.restype = _I
@@ -143,9 +145,41 @@ def _image(img: torch.Tensor, dtype=torch.uint8):
     return img, H, W, max(ld, W)
 
 
+def set_tile_table(rows):
+    """Install the tiling table of the single-image calls: rows of (largest h,
+    largest W, strip rows, threads), e.g. from ``tune.autotune_plain``; an
+    empty list removes it (``bz_set_tile_table``)."""
+    flat = [int(v) for r in rows for v in r]
+    if len(flat) != 4 * len(rows):
+        raise ValueError("each row holds four ints")
+    arr = (_I * max(len(flat), 1))(*flat)
+    _check(lib.bz_set_tile_table(ctypes.cast(arr, ctypes.POINTER(_I)), len(rows)), "bz_set_tile_table")
+
+
+_tiling_done = False
+
+
+def _tiling():
+    """On the first single-image call of the process: unless BZ_TILE_S or
+    BZ_TILE_THREADS is set, install the autotuner's cached table for this
+    device, if there is a readable one (a missing or corrupt cache leaves the
+    built-in plan)."""
+    global _tiling_done
+    if _tiling_done:
+        return
+    _tiling_done = True
+    if os.environ.get("BZ_TILE_S") or os.environ.get("BZ_TILE_THREADS"):
+        return
+    from . import tune
+    rows = tune.cached_plain_rows()
+    if rows:
+        set_tile_table(rows)
+
+
 def window_sums(img: torch.Tensor, h: int, w: int):
     """Exact window sums S1 = sum I, S2 = sum I^2 (uint32 values held in int32
     tensors; view them as unsigned).  Returns (S1, S2)."""
+    _tiling()
     img, H, W, ld = _image(img)
     S1 = torch.empty((H, W), dtype=torch.int32, device=img.device)
     S2 = torch.empty((H, W), dtype=torch.int32, device=img.device)
@@ -156,6 +190,7 @@ def window_sums(img: torch.Tensor, h: int, w: int):
 
 def window_mean_std(img: torch.Tensor, h: int, w: int):
     """Window mean and population standard deviation (float32)."""
+    _tiling()
     img, H, W, ld = _image(img)
     m = torch.empty((H, W), dtype=torch.float32, device=img.device)
     s = torch.empty((H, W), dtype=torch.float32, device=img.device)
@@ -208,6 +243,7 @@ def sauvola(img: torch.Tensor, h: int, w: int, k: float = 0.5, R: float = 128.0,
             stats: bool = True, mask=None, mean=None, std=None):
     """Sauvola mask (1 where I < m (1 + k (s/R - 1))); with ``stats`` also the
     float32 window mean and standard deviation.  Returns (mask, mean, std)."""
+    _tiling()
     img, H, W, ld = _image(img)
     mask, mean, std = _outputs(img, H, W, stats, mask, mean, std)
     ld_ms = _ld(mean, W) if mean is not None else 0
@@ -221,6 +257,7 @@ def sauvola(img: torch.Tensor, h: int, w: int, k: float = 0.5, R: float = 128.0,
 def niblack(img: torch.Tensor, h: int, w: int, k: float = -0.2, stats: bool = True,
             mask=None, mean=None, std=None):
     """Niblack mask (1 where I < m + k s); returns (mask, mean, std)."""
+    _tiling()
     img, H, W, ld = _image(img)
     mask, mean, std = _outputs(img, H, W, stats, mask, mean, std)
     ld_ms = _ld(mean, W) if mean is not None else 0
@@ -412,6 +449,7 @@ def binarize_streamed(img: torch.Tensor, h: int, w: int, method: str = "sauvola"
         raise ValueError("method must be 'sauvola' or 'niblack'")
     if axis not in _AXES:
         raise ValueError("axis must be 'auto', 'rows' or 'columns'")
+    _tiling()
     ld = _host_image(img, "img")
     H, W = img.shape
     if out is None:
@@ -487,6 +525,7 @@ def table1_threshold(img: torch.Tensor, h: int, w: int, method: str, params=None
         vals = [float(v) for v in (params or ())]
     if len(vals) != len(names):
         raise ValueError("%s takes parameters %s" % (method, names))
+    _tiling()
     img, H, W, ld = _image(img)
     if method in _NEEDS_GLOBAL and stats is None:
         stats = global_stats(img)

@@ -92,9 +92,36 @@ int env_int(const char *name)
     return e ? atoi(e) : 0;
 }
 
+// The tiling table installed by bz_set_tile_table: rows of (largest h,
+// largest W, strip rows, threads), kept sorted by (h, W).
+struct TileRule {
+    int hmax, wmax, strip, threads;
+};
+std::mutex g_tile_mu;
+std::vector<TileRule> g_tile_table;
+
+// Strip and block size for a plain call: the environment's overrides, else
+// the first table row whose class holds (h, W), else 0 (the built-in plan;
+// a row's 0 also keeps the built-in choice of that parameter).
+void tile_choice(int h, int W, int &strip, int &threads)
+{
+    strip = env_int("BZ_TILE_S");
+    threads = env_int("BZ_TILE_THREADS");
+    if (strip > 0 || threads > 0) return;
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    for (const TileRule &t : g_tile_table)
+        if (h <= t.hmax && W <= t.wmax) {
+            strip = t.strip;
+            threads = t.threads;
+            return;
+        }
+}
+
 bz_status run_box(BoxJob &j, hipStream_t stream)
 {
-    plan_box(j, env_int("BZ_TILE_S"), env_int("BZ_TILE_THREADS"));
+    int strip, threads;
+    tile_choice(j.h, j.W, strip, threads);
+    plan_box(j, strip, threads);
     if (inject_launch_fault()) return BZ_ERR_HIP;
     return hip_status(launch_box(j, stream));
 }
@@ -555,6 +582,24 @@ bz_status bz_bernsen_noalloc(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int
     if (sa != BZ_OK) return sa;
     return extremes_call(I, H, W, ld_I, h, w, contrast_min, mask, ld_mask, mn, mx, ld_mm, ws,
                          NOALLOC_SCRATCH_BYTES, stream);
+}
+
+bz_status bz_set_tile_table(const int *rows, int count)
+{
+    if (count < 0 || (count > 0 && rows == nullptr) || count > 4096) return BZ_ERR_INVALID;
+    std::vector<TileRule> t((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const int *r = rows + 4 * (size_t)i;
+        if (r[0] < 1 || r[1] < 1 || r[2] < 0 || r[3] < 0 || r[3] > MAX_THREADS || r[3] % 64 != 0)
+            return BZ_ERR_INVALID;
+        t[(size_t)i] = TileRule{r[0], r[1], r[2], r[3]};
+    }
+    std::stable_sort(t.begin(), t.end(), [](const TileRule &a, const TileRule &b) {
+        return a.hmax != b.hmax ? a.hmax < b.hmax : a.wmax < b.wmax;
+    });
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile_table.swap(t);
+    return BZ_OK;
 }
 
 size_t bz_batched_workspace_size(int count)

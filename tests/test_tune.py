@@ -27,3 +27,38 @@ def test_strips_for_table_and_defaults():
     assert got == [24, tune.default_strip(31), tune.default_strip(75), tune.default_strip(201)]
     table2 = {c: 40 for c in tune.WINDOW_CLASSES}
     assert tune.strips_for(params, table2) == [40, 40, 40, 40]
+
+
+DEV = "AMD Instinct MI355X"
+
+
+@pytest.mark.parametrize("text", ["", "{", "not json", "[1, 2, 3]", '{"%s": 7}' % DEV,
+                                  '{"%s": {"batch": "x"}}' % DEV, '{"%s": {"batch": {"15": "a"}}}' % DEV,
+                                  '{"%s": {"batch": {"15": 0}}}' % DEV,
+                                  '{"%s": {"plain": [[15, 1024, 8]]}}' % DEV,
+                                  '{"%s": {"plain": [[15, 1024, 8, 100]]}}' % DEV,
+                                  '{"%s": {"plain": "rows"}}' % DEV])
+@pytest.mark.parametrize("kind", ["batch", "plain"])
+def test_corrupt_or_foreign_cache_reads_as_missing(tmp_path, text, kind):
+    # a cache the tuner cannot use is ignored (the calls keep the built-in
+    # plans and the tuner measures again), never an error
+    p = tmp_path / "tilings.json"
+    p.write_text(text)
+    assert tune.load_table(str(p), DEV, kind) is None
+    assert tune.load_table(str(tmp_path / "missing.json"), DEV, kind) is None
+
+
+def test_cache_round_trip_keeps_other_entries(tmp_path):
+    p = str(tmp_path / "sub" / "tilings.json")
+    tune.save_table(p, DEV, "batch", {15: 24, 63: 48})
+    tune.save_table(p, DEV, "plain", [[15, 1024, 8, 256], [257, 8192, 0, 0]])
+    tune.save_table(p, "other device", "batch", {31: 32})
+    assert tune.load_table(p, DEV, "batch") == {15: 24, 63: 48}
+    assert tune.load_table(p, DEV, "plain") == [[15, 1024, 8, 256], [257, 8192, 0, 0]]
+    assert tune.load_table(p, "other device", "batch") == {31: 32}
+    assert tune.load_table(p, "other device", "plain") is None
+    # a corrupt file is replaced by the next save
+    with open(p, "w") as f:
+        f.write("{garbage")
+    tune.save_table(p, DEV, "batch", {15: 16})
+    assert tune.load_table(p, DEV, "batch") == {15: 16}
