@@ -22,12 +22,19 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("H,W,h,w,c", [(384, 512, 31, 31, 15), (203, 301, 9, 40, 20), (1, 1, 3, 3, 0),
-                                       (70, 4100, 15, 5, 30), (100, 90, 257, 257, 15), (64, 64, 1, 1, 0),
-                                       (1536, 2048, 32, 32, 15)])
-def test_bernsen_matches_oracle(bz, H, W, h, w, c):
+# windows up to 64 x 64 take the single-launch tile form; larger ones (and
+# BZ_EXT_FUSED=0) the two passes through the transposed field
+CASES = [(384, 512, 31, 31, 15), (203, 301, 9, 40, 20), (1, 1, 3, 3, 0), (70, 4100, 15, 5, 30),
+         (100, 90, 257, 257, 15), (64, 64, 1, 1, 0), (1536, 2048, 32, 32, 15), (130, 129, 64, 64, 10),
+         (131, 200, 65, 64, 10), (200, 131, 64, 65, 10), (65, 65, 2, 63, 5), (63, 257, 64, 1, 0)]
+
+
+@pytest.mark.parametrize("fused", ["1", "0"])
+@pytest.mark.parametrize("H,W,h,w,c", CASES)
+def test_bernsen_matches_oracle(bz, monkeypatch, fused, H, W, h, w, c):
+    monkeypatch.setenv("BZ_EXT_FUSED", fused)
     I = gen_document(H, W, 90 + H, noise=10.0, stain=True)
-    print("bernsen", H, W, h, w, c, flush=True)
+    print("bernsen", H, W, h, w, c, "fused", fused, flush=True)
     mask, mn, mx = bz.bernsen(dev(I), h, w, c)
     torch.cuda.synchronize()
     rmask, rmn, rmx = oracle.bernsen(I, h, w, c)
