@@ -100,6 +100,27 @@ def cpu_baseline(I, h, w, k, R, seconds):
     nproc = os.cpu_count() or 1
     threads = max(1, min(16, nproc))
     mpixn, repsn, dtn = oracle.time_recursive_sauvola_bands(I, h, w, k, R, threads, min_seconds=seconds / 2)
+    # the oracle's other paths, one thread each, on bounded samples of their
+    # workloads: the direct definition (Theta(H W h w)) on the whole 512 x 384
+    # page at h = w = 32, and the sliding-histogram quantiles on the first
+    # 256 rows of the 2048 x 1536 page (as a 256 x 2048 image)
+    from docgen import gen_document
+    others = {}
+    I0 = gen_document(384, 512, 1)
+    t0 = time.perf_counter()
+    S1, S2 = oracle.sums_direct(I0, 32, 32)
+    oracle.threshold(I0, 32, 32, oracle.SAUVOLA, 0.5, 128.0, S1=S1, S2=S2)
+    dt = time.perf_counter() - t0
+    others["direct_sauvola_512x384_h32"] = {"Mpix_s": round(I0.size / dt / 1e6, 3), "seconds": round(dt, 3),
+                                            "threads": 1, "sample": "the whole page once"}
+    Iq = np.ascontiguousarray(gen_document(1536, 2048, 3, noise=10.0, stain=True)[:256])
+    for qwin in (32, 101):
+        t0 = time.perf_counter()
+        oracle.quantile_hist(Iq, qwin, qwin, 0.5)
+        dt = time.perf_counter() - t0
+        others["quantile_hist_h%d_q0.5" % qwin] = {"Mpix_s": round(Iq.size / dt / 1e6, 3), "seconds": round(dt, 3),
+                                                   "threads": 1,
+                                                   "sample": "rows 0-255 of the 2048x1536 page, once"}
     return {
         "value": round(mpixn / 1000.0, 6),
         "unit": "Gpix/s",
@@ -111,6 +132,7 @@ def cpu_baseline(I, h, w, k, R, seconds):
         "single_thread_value": round(mpix1 / 1000.0, 6),
         "nproc": nproc,
         "cpu_model": cpu_model(),
+        "other_oracle_paths": others,
     }
 
 
