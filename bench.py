@@ -279,6 +279,7 @@ def extras(sets, host, args, batch_pages=None):
     def guarded(name, fn):
         if only is not None and name not in only:
             return
+        print("extra: %s" % name, file=sys.stderr, flush=True)
         try:
             out[name] = fn()
         except Exception as e:  # report, do not abort the bench line
