@@ -181,6 +181,14 @@ def _loop_us(fn, n, warm=3):
     return a.elapsed_time(b) * 1e3 / n
 
 
+def ragged_batch_file(suffix: str) -> str:
+    """A file under the temp directory keyed by the ragged-batch recipe."""
+    import tempfile
+    from docgen import batch_specs
+    key = hashlib.sha256(json.dumps(batch_specs(), sort_keys=True).encode()).hexdigest()[:16]
+    return os.path.join(tempfile.gettempdir(), "bz_ragged_batch_%s%s" % (key, suffix))
+
+
 def ragged_batch_pages(workers: int = 8):
     """The 256 pages of the ragged-batch recipe (docgen.batch_specs), each
     generated from its own seed (docgen.gen_batch), and their parameters.
@@ -189,11 +197,9 @@ def ragged_batch_pages(workers: int = 8):
     by the recipe, so that a later run maps them instead of generating them
     again: counter runs start after the profiler has initialised the GPU and
     so must not start worker processes (they pass workers=1)."""
-    import tempfile
     from docgen import batch_specs, gen_batch
     specs = batch_specs()
-    key = hashlib.sha256(json.dumps(specs, sort_keys=True).encode()).hexdigest()[:16]
-    path = os.path.join(tempfile.gettempdir(), "bz_ragged_batch_%s.npy" % key)
+    path = ragged_batch_file(".npy")
     sizes = [d["H"] * d["W"] for d in specs]
     flat = None
     if os.path.exists(path):
@@ -365,10 +371,15 @@ def extras(sets, host, args, batch_pages=None):
         from paper_1905_13038_amd import tune
         imgs, params = ragged_batch_inputs(sets[0][0].device, batch_pages)
         tot = sum(int(t.numel()) for t in imgs)
-        table = tune.autotune()
-        strips = tune.strips_for(params, table)
-        plan = bz.BatchPlan(imgs, params, strips=strips)
+        plan = bz.BatchPlan(imgs, params)
         outs = plan.outputs()
+        default_us = _loop_us(lambda i: plan.run(), 10, warm=2)
+        synth = tune.autotune()
+        plan.replan(tune.strips_for(params, synth))
+        synth_us = _loop_us(lambda i: plan.run(), 10, warm=2)
+        table = tune.autotune_plan(plan, params)  # leaves the plan on its result
+        with open(ragged_batch_file("_strips.json"), "w") as f:  # for the counter runs
+            json.dump({str(c): v for c, v in table.items()}, f)
 
         def plain(i):
             for img, p, (mk, mn, sd) in zip(imgs, params, outs):
@@ -382,12 +393,11 @@ def extras(sets, host, args, batch_pages=None):
         run_us = _loop_us(lambda i: plan.run(), 10, warm=2)
         plan.capture()
         graph_us = _loop_us(lambda i: plan.replay(), 10, warm=2)
-        plan_d = bz.BatchPlan(imgs, params)
-        default_us = _loop_us(lambda i: plan_d.run(), 10, warm=2)
-        del plan_d
         return {"images": len(imgs), "Gpx": round(tot / 1e9, 4),
                 "graph_replay_us": round(graph_us, 1), "persistent_run_us": round(run_us, 1),
                 "persistent_run_default_strips_us": round(default_us, 1),
+                "persistent_run_synthetic_table_us": round(synth_us, 1),
+                "synthetic_strip_table": {str(c): s_ for c, s_ in sorted(synth.items())},
                 "plain_calls_us": round(plain_us, 1),
                 "graph_Gpix_s": round(tot / graph_us / 1e3, 1),
                 "plain_Gpix_s": round(tot / plain_us / 1e3, 1),
@@ -630,9 +640,15 @@ def main():
 
     if args.pmc:
         if args.pmc_workload == "batch":
+            # the strips the timed batch measured on itself (bench.py's batch
+            # run leaves them in the temp directory), else the defaults
             from paper_1905_13038_amd import tune
             imgs, params = ragged_batch_inputs(dev, batch_pages)
-            plan = bz.BatchPlan(imgs, params, strips=tune.strips_for(params, tune.autotune()))
+            table = None
+            if os.path.exists(ragged_batch_file("_strips.json")):
+                with open(ragged_batch_file("_strips.json")) as f:
+                    table = {int(c): int(v) for c, v in json.load(f).items()}
+            plan = bz.BatchPlan(imgs, params, strips=tune.strips_for(params, table))
             for i in range(3):
                 plan.run()
         elif args.pmc_workload == "soft":

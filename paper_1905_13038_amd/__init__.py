@@ -327,12 +327,18 @@ class BatchPlan:
         n = len(images)
         self.ws_bytes = int(lib.bz_batched_workspace_size(n))
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.replan(strips)
+
+    def replan(self, strips=None):
+        """Plan the same images and outputs again with other strip heights
+        (None: the library's defaults); a captured graph is dropped."""
+        n = len(self.images)
         if strips is not None:
             arr = (_I * n)(*[int(x) for x in strips])
             sp = ctypes.cast(arr, ctypes.POINTER(_I))
         else:
             sp = None
-        _check(lib.bz_batched_plan(items, n, sp, self.workspace.data_ptr(), self.ws_bytes,
+        _check(lib.bz_batched_plan(self._items, n, sp, self.workspace.data_ptr(), self.ws_bytes,
                                    _stream(self.workspace)), "bz_batched_plan")
         self.graph = None
 

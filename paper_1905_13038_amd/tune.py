@@ -5,9 +5,11 @@ A batched launch processes each image in tiles of one strip of rows; every
 strip first primes its column sums over the h - 1 rows above and below its
 first row, so short strips waste priming work and tall strips leave fewer
 tiles to balance across the persistent grid.  ``autotune`` measures, per
-window-size class, the batch time of a few candidate strip heights on the
-device; ``strips_for`` maps the images of a batch to strip heights from that
-table (or from the library's built-in default when no table is given).
+window-size class, the batch time of a few candidate strip heights on a
+synthetic batch and caches the table; ``autotune_plan`` tunes the classes of
+one planned batch on that batch itself; ``strips_for`` maps the images of a
+batch to strip heights from a table (or from the library's built-in default
+when no table is given).
 
 A single-image call runs one tile per strip of rows and block of columns;
 ``autotune_plain`` measures, per window-size class and width class, candidate
@@ -193,6 +195,31 @@ def autotune(count: int = 64, H: int = 1536, W: int = 1536, candidates=CANDIDATE
     return table
 
 
+def autotune_plan(plan, params, candidates=CANDIDATES, reps: int = 5, min_gain: float = 0.005):
+    """Tune the strips of one planned batch on the batch itself: starting
+    from the built-in strips, each window class present takes in turn the
+    candidate that makes the whole launch fastest (kept only if it gains at
+    least ``min_gain``).  Leaves ``plan`` planned with the result and returns
+    the table {class: strip} (classes left at the built-in strip are absent)."""
+    classes = sorted(set(window_class(int(p["h"])) for p in params))
+    table = {}
+    plan.replan(strips_for(params, table))
+    best = _time(plan.run, reps)
+    for c in classes:
+        pick = None
+        for s in candidates:
+            trial = dict(table)
+            trial[c] = s
+            plan.replan(strips_for(params, trial))
+            t = _time(plan.run, reps)
+            if t < best * (1.0 - min_gain):
+                best, pick = t, s
+        if pick is not None:
+            table[c] = pick
+    plan.replan(strips_for(params, table))
+    return table
+
+
 def autotune_plain(H: int = 3072, classes=WINDOW_CLASSES, widths=WIDTH_CLASSES, strips=PLAIN_STRIPS,
                    threads=PLAIN_THREADS, reps: int = 5, cache_path: str | None = _DEFAULT_CACHE,
                    refresh: bool = False, device=None):
@@ -260,6 +287,6 @@ def cached_plain_rows(cache_path: str | None = _DEFAULT_CACHE, device=None):
     return load_table(cache_path, name, "plain")
 
 
-__all__ = ["autotune", "autotune_plain", "strips_for", "window_class", "default_strip", "load_table",
+__all__ = ["autotune", "autotune_plan", "autotune_plain", "strips_for", "window_class", "default_strip", "load_table",
            "save_table", "cached_plain_rows", "WINDOW_CLASSES", "WIDTH_CLASSES", "CANDIDATES",
            "PLAIN_STRIPS", "PLAIN_THREADS"]

@@ -147,6 +147,26 @@ def test_autotuned_strips(bz):
         assert torch.equal(mk, mk0) and torch.equal(m, m0) and torch.equal(s, s0)
 
 
+def test_in_situ_tuning_and_replan(bz):
+    # autotune_plan re-plans the batch on its own outputs for each trial and
+    # leaves it on the chosen strips; the results equal the plain calls
+    from paper_1905_13038_amd import tune
+    imgs, params = small_batch()
+    plan = bz.BatchPlan(imgs, params)
+    table = tune.autotune_plan(plan, params, candidates=(8, 64), reps=1)
+    assert set(table) <= {tune.window_class(int(p["h"])) for p in params}
+    assert all(v in (8, 64) for v in table.values())
+    for strips in (None, [5] * len(imgs)):
+        plan.replan(strips)
+        for mask, m, s in plan.outputs():
+            mask.zero_()
+        plan.run()
+        torch.cuda.synchronize()
+        for img, p, (mk, m, s) in zip(imgs, params, plan.outputs()):
+            mk0, m0, s0 = plain(bz, img, p)
+            assert same(mk, mk0) and same(m, m0) and same(s, s0)
+
+
 def test_plan_outputs_rows_on_64_byte_boundaries(bz):
     # BatchPlan pads its output rows so that each row starts on a 64-byte
     # boundary; the values match plain calls with contiguous outputs
