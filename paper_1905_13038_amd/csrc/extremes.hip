@@ -287,7 +287,7 @@ __device__ __forceinline__ void ext_pivot_block(const uint16_t *__restrict__ src
 __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict__ I, int64_t ldI, int H, int W, int h,
                                                       int w, int o, int l, int ntx, uint8_t *__restrict__ mn,
                                                       uint8_t *__restrict__ mx, int64_t ldE, int cmin,
-                                                      uint8_t *__restrict__ mask, int64_t ldM, bool vec)
+                                                      uint8_t *__restrict__ mask, int64_t ldM, int flags)
 {
     extern __shared__ uint16_t sh[];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -304,9 +304,44 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
     const int ty0 = y0 - o + 1, tx0 = x0 - l + 1;
     const int tid = threadIdx.x;
 
-    // 1. input tile: thread (c, r0) takes column c < CW (at most 127) of rows
-    // r0, r0 + 2, ...
-    {
+    const bool vout = flags & 1, vin = flags & 2;
+    // one descriptor over the whole image (vin: 4-byte aligned base and
+    // stride, and the image under 2^31 bytes), rounded up to the aligned
+    // word holding its last byte
+    const __amdgpu_buffer_rsrc_t dimg = rsrc(I, vin ? (uint32_t)((int64_t)(H - 1) * ldI + ((W + 3) & ~3)) : 0u);
+
+    // 1. input tile.  vin: aligned dwords, one per thread and pass (the
+    // columns from tx0 rounded down to a multiple of 4), each byte kept where
+    // it lies in the tile and the image; otherwise thread (c, r0) takes
+    // column c < CW (at most 127) of rows r0, r0 + 2, ..., one byte each
+    if (vin) {
+        const int m = tx0 & 3, xb = tx0 - m;
+        const int ND = (CW + m + 3) >> 2, N = RH * ND;
+        for (int i0 = tid; i0 < N; i0 += EXT_FLOADS * EXT_FT) {
+            uint32_t v[EXT_FLOADS];
+#pragma unroll
+            for (int q = 0; q < EXT_FLOADS; ++q) {
+                const int i = min(i0 + q * EXT_FT, N - 1), r = i / ND, d = i - r * ND;
+                const int yy = min(max(ty0 + r, 0), H - 1), x = xb + 4 * d;
+                const uint32_t off = x >= 0 ? (uint32_t)((int64_t)yy * ldI + x) : 0x80000000u;
+                v[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(dimg, (int)off, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < EXT_FLOADS; ++q) {
+                const int i = i0 + q * EXT_FT;
+                if (i >= N) break;
+                const int r = i / ND, d = i - r * ND, yy = ty0 + r;
+                const bool rin = yy >= 0 && yy < H;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = 4 * d - m + j, xx = tx0 + c;
+                    if (c < 0 || c >= CW) continue;
+                    const uint32_t e = (v[q] >> (8 * j)) & 0xffu;
+                    tin[r * CP + c] = (uint16_t)((rin && xx >= 0 && xx < W) ? (e | ((255u - e) << 8)) : 0u);
+                }
+            }
+        }
+    } else {
         const int c = tid & 127, r0 = tid >> 7;
         const int xx = tx0 + c;
         const bool cin = c < CW && xx >= 0 && xx < W;
@@ -369,9 +404,19 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = tr + (EXT_FT / QPR) * k;
-        const uint8_t *irow = I + (int64_t)min(y0 + t, H - 1) * ldI;
+        const int yc = min(y0 + t, H - 1);
+        if (vin) {
+            // the aligned dword of columns x0 + xq .. +3 (past W: unused)
+            const uint32_t q4 = mask ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                                           dimg, (int)((int64_t)yc * ldI + x0 + xq), 0, 0)
+                                     : 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) iv[k][j] = mask ? irow[min(x0 + xq + j, W - 1)] : 0u;
+            for (int j = 0; j < 4; ++j) iv[k][j] = (q4 >> (8 * j)) & 0xffu;
+        } else {
+            const uint8_t *irow = I + (int64_t)yc * ldI;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) iv[k][j] = mask ? irow[min(x0 + xq + j, W - 1)] : 0u;
+        }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -388,7 +433,7 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
         }
         uint8_t *pmx = mx + (int64_t)yy * ldE + xx, *pmn = mn + (int64_t)yy * ldE + xx;
         uint8_t *pmk = mask ? mask + (int64_t)yy * ldM + xx : nullptr;
-        if (vec && xx + 3 < W) {
+        if (vout && xx + 3 < W) {
             *(uint32_t *)pmx = hi[0] | (hi[1] << 8) | (hi[2] << 16) | (hi[3] << 24);
             *(uint32_t *)pmn = lo[0] | (lo[1] << 8) | (lo[2] << 16) | (lo[3] << 24);
             if (mask) *(uint32_t *)pmk = mk[0] | (mk[1] << 8) | (mk[2] << 16) | (mk[3] << 24);
@@ -432,10 +477,13 @@ hipError_t launch_extremes(const uint8_t *I, int64_t ldI, int H, int W, int h, i
                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (ea != hipSuccess) return ea;
         }
-        const bool vec = ((uintptr_t)mn & 3u) == 0 && ((uintptr_t)mx & 3u) == 0 && (ldE & 3) == 0 &&
-                         (mask == nullptr || (((uintptr_t)mask & 3u) == 0 && (ldM & 3) == 0));
+        const bool vout = ((uintptr_t)mn & 3u) == 0 && ((uintptr_t)mx & 3u) == 0 && (ldE & 3) == 0 &&
+                          (mask == nullptr || (((uintptr_t)mask & 3u) == 0 && (ldM & 3) == 0));
+        const bool vin = ((uintptr_t)I & 3u) == 0 && (ldI & 3) == 0 && (int64_t)(H - 1) * ldI + W + 3 < (1ll << 31);
+        const char *fv = getenv("BZ_EXT_VEC");  // 0: byte loads and stores (tests)
+        const int flags = (fv && atoi(fv) == 0) ? 0 : (vout ? 1 : 0) | (vin ? 2 : 0);
         hipLaunchKernelGGL(k_ext_fused, dim3(ntx * nty), dim3(EXT_FT), lds, stream, I, ldI, H, W, h, w, o, l, ntx, mn,
-                           mx, ldE, cmin, mask, ldM, vec);
+                           mx, ldE, cmin, mask, ldM, flags);
         return hipGetLastError();
     }
     const int Sv = ext_strips(h), Sh = ext_strips(w);

@@ -29,17 +29,35 @@ CASES = [(384, 512, 31, 31, 15), (203, 301, 9, 40, 20), (1, 1, 3, 3, 0), (70, 41
          (131, 200, 65, 64, 10), (200, 131, 64, 65, 10), (65, 65, 2, 63, 5), (63, 257, 64, 1, 0)]
 
 
-@pytest.mark.parametrize("fused", ["1", "0"])
+@pytest.mark.parametrize("form", ["fused", "fused_bytes", "two_pass"])
 @pytest.mark.parametrize("H,W,h,w,c", CASES)
-def test_bernsen_matches_oracle(bz, monkeypatch, fused, H, W, h, w, c):
-    monkeypatch.setenv("BZ_EXT_FUSED", fused)
+def test_bernsen_matches_oracle(bz, monkeypatch, form, H, W, h, w, c):
+    # fused: dword loads and stores where rows are 4-byte aligned (W a
+    # multiple of 4 here); fused_bytes: BZ_EXT_VEC=0, byte accesses only
+    monkeypatch.setenv("BZ_EXT_FUSED", "0" if form == "two_pass" else "1")
+    monkeypatch.setenv("BZ_EXT_VEC", "0" if form == "fused_bytes" else "1")
     I = gen_document(H, W, 90 + H, noise=10.0, stain=True)
-    print("bernsen", H, W, h, w, c, "fused", fused, flush=True)
+    print("bernsen", H, W, h, w, c, form, flush=True)
     mask, mn, mx = bz.bernsen(dev(I), h, w, c)
     torch.cuda.synchronize()
     rmask, rmn, rmx = oracle.bernsen(I, h, w, c)
     assert np.array_equal(mn.cpu().numpy(), rmn)
     assert np.array_equal(mx.cpu().numpy(), rmx)
+    assert np.array_equal(mask.cpu().numpy(), rmask)
+
+
+@pytest.mark.parametrize("off,ld", [(0, 2052), (4, 2056), (1, 2051), (0, 2050)])
+def test_bernsen_strided_input_and_alignment(bz, off, ld):
+    # aligned views take the dword tile loads, the others the byte loads
+    H, W = 300, 2040
+    I = gen_document(H, W, 5 + off, noise=10.0, stain=True)
+    buf = torch.zeros(H * ld + off + 8, dtype=torch.uint8, device="cuda")
+    view = buf[off:off + H * ld].view(H, ld)[:, :W]
+    view.copy_(dev(I))
+    mask, mn, mx = bz.bernsen(view, 33, 17, 12)
+    torch.cuda.synchronize()
+    rmask, rmn, rmx = oracle.bernsen(I, 33, 17, 12)
+    assert np.array_equal(mn.cpu().numpy(), rmn) and np.array_equal(mx.cpu().numpy(), rmx)
     assert np.array_equal(mask.cpu().numpy(), rmask)
 
 
