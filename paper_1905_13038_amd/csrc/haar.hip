@@ -275,25 +275,34 @@ __global__ __launch_bounds__(64) void k_haar_fused(const uint8_t *__restrict__ I
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(d, 4 * lane + 256 * q, 0, 0);
     };
 
-    // G of row i0: the signed sum of the kv a rows below it
+    // G of row i0: the signed sum of the kv a rows below it.  Each cell's a
+    // rows are summed bytewise into 16-bit fields (even and odd bytes of a
+    // dword apart; a <= 257 rows of at most 255 stay below 2^16), then
+    // added to G with the cell's sign.
     uint32_t g[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) g[c] = 0u;
 #pragma unroll
     for (int m = 0; m < KV; ++m) {
         const int r0 = i0 + m * a;
+        uint32_t ev[NDW], od[NDW];
+#pragma unroll
+        for (int q = 0; q < NDW; ++q) ev[q] = od[q] = 0u;
 #pragma unroll 4
         for (int r = 0; r < a; ++r) {
             const __amdgpu_buffer_rsrc_t d = row_rsrc(r0 + r);
 #pragma unroll
             for (int q = 0; q < NDW; ++q) {
                 const uint32_t v = load(d, q);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const uint32_t e = (v >> (8 * c)) & 0xffu;
-                    g[4 * q + c] = (m & 1) ? g[4 * q + c] - e : g[4 * q + c] + e;
-                }
+                ev[q] += v & 0x00ff00ffu;
+                od[q] += __builtin_amdgcn_perm(0u, v, 0x0c030c01u);  // bytes 1, 3 into 0, 2
             }
+        }
+#pragma unroll
+        for (int q = 0; q < NDW; ++q) {
+            const uint32_t cs[4] = {ev[q] & 0xffffu, od[q] & 0xffffu, ev[q] >> 16, od[q] >> 16};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) g[4 * q + c] = (m & 1) ? g[4 * q + c] - cs[c] : g[4 * q + c] + cs[c];
         }
     }
 

@@ -65,6 +65,13 @@ def test_haar_extremes_of_the_value_range(bz):
     I[:, :257] = 255
     check(bz, I, a, b, "edge_h")
     check(bz, I[:, ::-1].copy(), a, b, "edge_h")
+    # 257-row cells of 255 in the single-launch form (its cell sums fill 16
+    # bits exactly: 255 * 257 = 65535)
+    J = np.zeros((514, 300), np.uint8)
+    J[:257] = 255
+    check(bz, J, 257, 7, "edge_v")
+    check(bz, J[::-1].copy(), 257, 7, "edge_v")
+    check(bz, np.full((257 * 3, 64), 255, np.uint8), 257, 5, "line_v")
 
 
 @pytest.mark.parametrize("kind,a", [("edge_h", 12), ("checker", 12), ("line_v", 12), ("line_v", 48)])
