@@ -253,9 +253,9 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
 // float32 input in the ranges used, are within 2u max(1, |log2 x|)
 // (absolute) and 1.42u (relative); x is within 4u, so x^g is within
 // (1.5 + |g|(6.1 + 2.1 |log2 x|))u.  The guard G mag takes 2^-18 (64u) for
-// Wolf and NICK, 2^-17 for Phansalkar (mag scaled by 1 + |q m|), 2^-16 for
-// Rais and 2^-19 for Feng (mag scaled by 2 + |g|(1 + |log2 x|)): a factor of
-// 5 or more over the bounds.  Where |I - t32| > G mag the float32 and
+// Wolf, 2^-19 (32u) for NICK, 2^-18 for Phansalkar (mag scaled by 1 + |q m|),
+// 2^-17 for Rais and 2^-19 for Feng (mag scaled by 2 + |g|(1 + |log2 x|)):
+// a factor of 4.5 or more over the bounds.  Where |I - t32| > G mag the float32 and
 // binary64 decisions agree; other pixels, and any non-finite value, go to
 // table1_below.
 struct T1Fast {
@@ -281,10 +281,10 @@ __device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, dou
     f.L = (float)L;
     f.MS = (float)M * (float)S;
     f.pow0 = tp[3] > 0.0 ? 0.0f : tp[3] == 0.0 ? 1.0f : __builtin_inff();
-    f.G = rule == T1_WOLF || rule == T1_NICK ? 0x1p-18f
-          : rule == T1_PHANSALKAR             ? 0x1p-17f
-          : rule == T1_RAIS                   ? 0x1p-16f
-                                              : 0x1p-19f;
+    f.G = rule == T1_WOLF                         ? 0x1p-18f
+          : rule == T1_NICK || rule == T1_FENG    ? 0x1p-19f
+          : rule == T1_PHANSALKAR                 ? 0x1p-18f
+                                                  : 0x1p-17f;  // T1_RAIS
     return f;
 }
 
