@@ -119,10 +119,13 @@ size_t bz_extremes_workspace_size(int H, int W);
 
 /*
  * Window minimum and maximum of the clipped window (in-bounds pixels only;
- * the paper's local extremes, which it keeps with deques).  Two separable
- * passes through a 16-bit H x W field in `workspace` (DEVICE memory of at
- * least bz_extremes_workspace_size(H, W) bytes, 4-byte aligned, overlapping
- * no input or output).  mn, mx: uint8 H x W, row stride ld_out; exact.
+ * the paper's local extremes, which it keeps with deques).  Windows of at
+ * most 64 x 64 run in one launch with both separable passes in on-chip
+ * memory; larger ones take two passes through a 16-bit H x W field in
+ * `workspace`.  The workspace (DEVICE memory of at least
+ * bz_extremes_workspace_size(H, W) bytes, 4-byte aligned, overlapping no
+ * input or output) is checked either way.  mn, mx: uint8 H x W, row stride
+ * ld_out; exact.
  */
 bz_status bz_window_minmax(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int w, uint8_t *mn,
                            uint8_t *mx, ptrdiff_t ld_out, void *workspace, size_t ws_bytes,
@@ -143,8 +146,9 @@ bz_status bz_bernsen(const uint8_t *I, int H, int W, ptrdiff_t ld_I, int h, int 
 /*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid it): bz_bernsen without a workspace
- * argument.  The 16-bit field of the two passes lives in a device array of
- * the library, fixed at 32 MiB per GPU (held until the process ends), so
+ * argument.  The 16-bit field of the two passes (windows over 64 rows or
+ * columns) lives in a device array of the library, fixed at 32 MiB per GPU
+ * (held until the process ends), so
  * H W must not exceed bz_bernsen_noalloc_max_pixels() (16,777,216; larger
  * images return BZ_ERR_WORKSPACE).  The call allocates nothing; its first
  * call on a device looks up that device's array (BZ_ERR_HIP if the lookup
