@@ -66,3 +66,22 @@ def test_cached_rows_for_this_device(bz, tmp_path):
     with open(p, "w") as f:
         f.write("{corrupt")
     assert tune.cached_plain_rows(p) is None
+
+
+def test_autotune_plain_rows_are_valid_and_installable(bz, clean_table):
+    # a small measurement (two window classes, two widths, two strips, two
+    # block sizes): one row per class pair, each installable, outputs
+    # unchanged under the table
+    from paper_1905_13038_amd import tune
+    rows = tune.autotune_plain(H=256, classes=(15, 63), widths=(512, 2048), strips=(8, 24), threads=(256, 1024),
+                               reps=1, cache_path=None)
+    assert len(rows) == 4
+    for hmax, wmax, strip, threads in rows:
+        assert hmax in (15, 63) and wmax in (512, 2048)
+        assert strip in (0, 8, 24) and threads in (0, 256, 1024) and (strip == 0) == (threads == 0)
+    img = torch.from_numpy(gen_document(300, 1500, 77, noise=10.0, stain=True)).cuda()
+    ref = [t.clone() for t in bz.sauvola(img, 41, 41)]
+    bz.set_tile_table(rows)
+    got = bz.sauvola(img, 41, 41)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(got, ref))
