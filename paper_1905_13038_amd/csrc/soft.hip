@@ -37,6 +37,7 @@
 #include "internal.hpp"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 namespace bz {
@@ -509,6 +510,28 @@ __global__ __launch_bounds__(REDUCE_THREADS) void k_soft_reduce(const double *pa
     }
 }
 
+// Strip height of a phase (or the whole image when shorter): the forward
+// and the sums export take 8 rows, the backward's phases min(h, 32) rows and
+// at least 8.  env (8 .. 32 rows) overrides it for tuning.
+//
+// Measured on 32 float32 pages of 1024 x 1024, forward: 8-row strips took
+// 78-84 us at h = 9 .. 32 against 82-87 us for min(h, 32) rows, and 91 and
+// 104 us at h = 51 and 75 against 110 and 125 us for 32 rows.  An XCD then
+// holds the strips of one page at a time, all resident together, and the
+// priming rows of adjacent strips are shared through its L2.  The backward
+// measured slower with 8-row strips (BWD1 by 24 us at h = 32), so it keeps
+// the taller ones.
+void set_strip(SoftArgs &a, const char *env, bool forward)
+{
+    int strip = forward ? 8 : (a.h < 32 ? a.h : 32);
+    const char *e = getenv(env);
+    if (e && atoi(e) > 0) strip = atoi(e) > 32 ? 32 : atoi(e);
+    if (strip < 8) strip = 8;
+    if (strip > a.H) strip = a.H;
+    a.strip = strip;
+    a.nsy = (a.H + strip - 1) / strip;
+}
+
 // Tiling shared by the three phases: a single-wave tile when the row and
 // the window fit one, else four-wave tiles: one column tile when W fits,
 // else balanced tiles with a halo wide enough for either window orientation.
@@ -542,11 +565,7 @@ void plan_soft(SoftArgs &a)
     }
     // strips depend on the image geometry only, so an image gives the same
     // bits in any batch; the priming of a strip reads h rows beyond it
-    int strip = a.h < 32 ? a.h : 32;
-    if (strip < 8) strip = 8;
-    if (strip > a.H) strip = a.H;
-    a.strip = strip;
-    a.nsy = (a.H + strip - 1) / strip;
+    set_strip(a, "BZ_SOFT_STRIP_BWD", false);
     a.vec = (a.ld % 4 == 0) && (a.W % 4 == 0);
 }
 
@@ -593,6 +612,7 @@ hipError_t launch_soft_fwd(const float *I, int B, int H, int W, int64_t ld, int 
     a.w = w;
     a.tau = tau;
     plan_soft(a);
+    set_strip(a, "BZ_SOFT_STRIP", true);
     a.eo = a.o;
     a.eu = a.u;
     a.el = a.l;
@@ -618,6 +638,7 @@ hipError_t launch_soft_sums(const float *I, int B, int H, int W, int64_t ld, int
     a.w = w;
     a.tau = 1.0f;
     plan_soft(a);
+    set_strip(a, "BZ_SOFT_STRIP", true);
     a.eo = a.o;
     a.eu = a.u;
     a.el = a.l;
@@ -667,7 +688,8 @@ hipError_t launch_soft_bwd(const float *I, const float *gy, int B, int H, int W,
     a.er = a.l - 1;
     // the dense fields have row stride W: 16-byte loads need W % 4 == 0
     a.vec = (W % 4 == 0);
-    launch_phase<ADJ>(a, blocks, st);
+    set_strip(a, "BZ_SOFT_STRIP_ADJ", false);
+    launch_phase<ADJ>(a, B * a.ntx * a.nsy, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_soft_reduce, dim3(1), dim3(REDUCE_THREADS), 0, st, (const double *)a.part, B, per_img,
