@@ -109,7 +109,7 @@ __device__ __forceinline__ uint32_t ge_fields(uint32_t val, uint32_t K)
 constexpr int GROUP = 8;  // dwords of row bytes per group (32 window columns)
 
 // Byte q of the entering (ve) and leaving (vl) dwords at window column c0 + q.
-template <bool PACK, bool FULL, bool BOTH, int q>
+template <bool PACK, bool FULL, bool BOTH, int LSIGN, int q>
 __device__ __forceinline__ void group_bytes(uint32_t *hist, const Slot &slot, uint32_t ve, uint32_t vl, bool has_e,
                                             bool has_l, int c0, int wmax, int nc, int Q, int &lt)
 {
@@ -121,9 +121,9 @@ __device__ __forceinline__ void group_bytes(uint32_t *hist, const Slot &slot, ui
     lds_add(hist, off, oke ? inc : 0u);
     if (BOTH) {
         const bool okl = FULL || (ok && has_l);
-        bin_slot<q, -1>(vl, slot, off, inc);
+        bin_slot<q, LSIGN>(vl, slot, off, inc);
         lds_add(hist, off, okl ? inc : 0u);
-        if (!FULL) {
+        if (!FULL && LSIGN < 0) {
             const uint32_t v_e = (ve >> (8 * q)) & 0xffu, v_l = (vl >> (8 * q)) & 0xffu;
             lt += (int)(oke && v_e < (uint32_t)Q) - (int)(okl && v_l < (uint32_t)Q);
         }
@@ -136,8 +136,9 @@ __device__ __forceinline__ void group_bytes(uint32_t *hist, const Slot &slot, ui
 // both rows exist, so no byte needs a check, and lt is updated from the
 // group's byte counts; otherwise each byte is checked (a byte outside adds
 // zero) and compared.  BOTH false: only e is added, to the first window,
-// built with Q = 0 (no value lies below it).
-template <bool PACK, bool FULL, bool BOTH>
+// built with Q = 0 (no value lies below it).  LSIGN +1: l is added too (two
+// rows of the first window per round trip; lt stays 0).
+template <bool PACK, bool FULL, bool BOTH, int LSIGN>
 __device__ __forceinline__ void group_update(uint32_t *hist, const Slot &slot, const uint32_t *de, const uint32_t *dl,
                                              int se, int sl, bool has_e, bool has_l, int kbase, int wmax, int nc,
                                              int Q, int &lt)
@@ -148,16 +149,16 @@ __device__ __forceinline__ void group_update(uint32_t *hist, const Slot &slot, c
     for (int t = 0; t < GROUP; ++t) {
         const uint32_t ve = __builtin_amdgcn_alignbyte(de[t + 1], de[t], se);
         const uint32_t vl = BOTH ? __builtin_amdgcn_alignbyte(dl[t + 1], dl[t], sl) : 0u;
-        if (FULL && BOTH) {
+        if (FULL && BOTH && LSIGN < 0) {
             ge_e += ge_fields(ve, K);
             ge_l += ge_fields(vl, K);
         }
-        group_bytes<PACK, FULL, BOTH, 0>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 1>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 2>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
-        group_bytes<PACK, FULL, BOTH, 3>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, LSIGN, 0>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, LSIGN, 1>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, LSIGN, 2>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
+        group_bytes<PACK, FULL, BOTH, LSIGN, 3>(hist, slot, ve, vl, has_e, has_l, kbase + 4 * t, wmax, nc, Q, lt);
     }
-    if (FULL && BOTH) {
+    if (FULL && BOTH && LSIGN < 0) {
         // bytes below Q: entering minus leaving = (32 - ge_e) - (32 - ge_l)
         lt += (int)(((ge_l >> 8) & 0xffu) + (ge_l >> 24)) - (int)(((ge_e >> 8) & 0xffu) + (ge_e >> 24));
     }
@@ -168,8 +169,9 @@ __device__ __forceinline__ void group_update(uint32_t *hist, const Slot &slot, c
 // removed (has_e / has_l false: that row lies outside the image).  All
 // ds_bpermutes of a group are issued together, so the LDS round trips are
 // per group, not per dword.  clip: some lane's window is clipped by the
-// image border (nc < w).  BOTH false: only e is added (the first window).
-template <bool PACK, bool TWO, bool BOTH>
+// image border (nc < w).  BOTH false: only e is added (the first window);
+// LSIGN +1: e and l are both added (two rows of the first window).
+template <bool PACK, bool TWO, bool BOTH, int LSIGN = -1>
 __device__ __forceinline__ void slide_rows(uint32_t *hist, const Slot &slot, const RowBytes<TWO> &e, const RowBytes<TWO> &l, bool has_e,
                                            bool has_l, int rel, int nc, int wmax, bool clip, int Q, int &lt)
 {
@@ -187,9 +189,36 @@ __device__ __forceinline__ void slide_rows(uint32_t *hist, const Slot &slot, con
             dl[t] = BOTH ? l.dword(il + k / 4 + t) : 0u;
         }
         if (fast && k + 4 * GROUP <= wmax)
-            group_update<PACK, true, BOTH>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+            group_update<PACK, true, BOTH, LSIGN>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
         else
-            group_update<PACK, false, BOTH>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+            group_update<PACK, false, BOTH, LSIGN>(hist, slot, de, dl, se, sl, has_e, has_l, k, wmax, nc, Q, lt);
+    }
+}
+
+// Four rows of the first window per round trip: the bytes of rows a, b, c
+// and d are fetched before any of their atomics (every row exists).
+template <bool PACK, bool TWO>
+__device__ __forceinline__ void build_rows4(uint32_t *hist, const Slot &slot, const RowBytes<TWO> &a,
+                                            const RowBytes<TWO> &b, const RowBytes<TWO> &c, const RowBytes<TWO> &d,
+                                            int rel, int nc, int wmax, bool clip, int Q, int &lt)
+{
+    const int ba = a.sh + rel, bb = b.sh + rel, bc = c.sh + rel, bd = d.sh + rel;
+    for (int k = 0; k < wmax; k += 4 * GROUP) {
+        uint32_t da[GROUP + 1], db[GROUP + 1], dc[GROUP + 1], dd[GROUP + 1];
+#pragma unroll
+        for (int t = 0; t <= GROUP; ++t) {
+            da[t] = a.dword((ba >> 2) + k / 4 + t);
+            db[t] = b.dword((bb >> 2) + k / 4 + t);
+            dc[t] = c.dword((bc >> 2) + k / 4 + t);
+            dd[t] = d.dword((bd >> 2) + k / 4 + t);
+        }
+        if (!clip && k + 4 * GROUP <= wmax) {
+            group_update<PACK, true, true, 1>(hist, slot, da, db, ba & 3, bb & 3, true, true, k, wmax, nc, Q, lt);
+            group_update<PACK, true, true, 1>(hist, slot, dc, dd, bc & 3, bd & 3, true, true, k, wmax, nc, Q, lt);
+        } else {
+            group_update<PACK, false, true, 1>(hist, slot, da, db, ba & 3, bb & 3, true, true, k, wmax, nc, Q, lt);
+            group_update<PACK, false, true, 1>(hist, slot, dc, dd, bc & 3, bd & 3, true, true, k, wmax, nc, Q, lt);
+        }
     }
 }
 
@@ -402,15 +431,47 @@ __global__ __launch_bounds__(qwaves<PACK>() * QLANES) void k_quantile(QuantJob a
 
     int Q = 0;   // current answer
     int lt = 0;  // number of window values below Q
-    // histogram of the window of row y0
+    // histogram of the window of row y0.  Windows wider than 32 columns take
+    // four rows per pass (the bytes of all four are fetched before any of
+    // their atomics), narrower ones two (four measured slower there); the
+    // next rows are loaded ahead, and the last one to three rows go in a
+    // pair and singly
     {
         const int r0 = max(y0 - a.o + 1, 0), r1 = min(y0 + a.u, H - 1);
-        RowBytes<TWO> rb;
-        if (r0 <= r1) rb.load(rowp(r0), nb, lane);
-        for (int row = r0; row <= r1; ++row) {
-            RowBytes<TWO> cur = rb;
-            if (row < r1) rb.load(rowp(row + 1), nb, lane);
-            slide_rows<PACK, TWO, false>(hist, slot, cur, cur, true, false, rel, nc, wmax, clip, Q, lt);
+        const bool quads = wmax > 4 * PGROUP;  // wave-uniform
+        RowBytes<TWO> ra, rb, rc, rd;
+        if (r0 <= r1) ra.load(rowp(r0), nb, lane);
+        if (r0 + 1 <= r1) rb.load(rowp(r0 + 1), nb, lane);
+        if (quads && r0 + 2 <= r1) rc.load(rowp(r0 + 2), nb, lane);
+        if (quads && r0 + 3 <= r1) rd.load(rowp(r0 + 3), nb, lane);
+        int row = r0;
+        if (quads) {
+            for (; row + 3 <= r1; row += 4) {
+                const RowBytes<TWO> ca = ra, cb = rb, cc = rc, cd = rd;
+                if (row + 4 <= r1) ra.load(rowp(row + 4), nb, lane);
+                if (row + 5 <= r1) rb.load(rowp(row + 5), nb, lane);
+                if (row + 6 <= r1) rc.load(rowp(row + 6), nb, lane);
+                if (row + 7 <= r1) rd.load(rowp(row + 7), nb, lane);
+                build_rows4<PACK, TWO>(hist, slot, ca, cb, cc, cd, rel, nc, wmax, clip, Q, lt);
+            }
+            // rows row .. r1 (at most three) are in ra, rb, rc
+            if (row + 1 <= r1) {
+                slide_rows<PACK, TWO, true, 1>(hist, slot, ra, rb, true, true, rel, nc, wmax, clip, Q, lt);
+                if (row + 2 <= r1)
+                    slide_rows<PACK, TWO, false>(hist, slot, rc, rc, true, false, rel, nc, wmax, clip, Q, lt);
+            } else if (row <= r1) {
+                slide_rows<PACK, TWO, false>(hist, slot, ra, ra, true, false, rel, nc, wmax, clip, Q, lt);
+            }
+        } else {
+            for (; row <= r1; row += 2) {
+                const RowBytes<TWO> ca = ra, cb = rb;
+                if (row + 2 <= r1) ra.load(rowp(row + 2), nb, lane);
+                if (row + 3 <= r1) rb.load(rowp(row + 3), nb, lane);
+                if (row + 1 <= r1)
+                    slide_rows<PACK, TWO, true, 1>(hist, slot, ca, cb, true, true, rel, nc, wmax, clip, Q, lt);
+                else
+                    slide_rows<PACK, TWO, false>(hist, slot, ca, ca, true, false, rel, nc, wmax, clip, Q, lt);
+            }
         }
     }
 
