@@ -27,11 +27,14 @@ def run(bz, I, h, w, q):
 
 
 # odd widths give rows at every byte alignment; w = 189 and 201 take two
-# dwords of row bytes per lane, 257 x 257 windows one 32-bit word per bin
+# dwords of row bytes per lane, 257 x 257 windows one 32-bit word per bin;
+# windows wider than 32 build their first window four rows per pass, and the
+# last three cases leave 0, 1, 2 or 3 rows over in the strips' builds
 @pytest.mark.parametrize("H,W,h,w,q", [(37, 61, 8, 12, 0.1), (64, 64, 32, 32, 0.5), (50, 130, 101, 101, 0.1),
                                        (25, 70, 1, 1, 0.5), (45, 45, 16, 5, 0.75), (9, 200, 3, 40, 1.0),
                                        (200, 9, 40, 3, 0.0), (1, 1, 5, 5, 0.5), (30, 397, 9, 189, 0.5),
-                                       (41, 333, 5, 201, 0.25), (270, 301, 257, 257, 0.5)])
+                                       (41, 333, 5, 201, 0.25), (270, 301, 257, 257, 0.5),
+                                       (60, 150, 8, 36, 0.5), (70, 90, 12, 33, 0.3), (77, 140, 7, 35, 0.9)])
 def test_small_shapes(bz, H, W, h, w, q):
     I = gen_document(H, W, H * 31 + W, noise=10, stain=True)
     Q, mask = run(bz, I, h, w, q)

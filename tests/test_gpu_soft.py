@@ -50,11 +50,13 @@ def compare(bz, I, k, R, h, w, g):
 
 # single-wave tiles (rows of at most 256 columns, aligned and ragged, up to
 # the widest window they take) and four-wave tiles (wider rows or windows,
-# one or several tiles per row)
+# one or several tiles per row); images shorter than the forward's 8-row
+# strips and ragged last strips
 @pytest.mark.parametrize("B,H,W,h,w", [(2, 64, 80, 7, 7), (3, 40, 33, 6, 9), (1, 100, 1500, 32, 32),
                                        (2, 300, 50, 75, 4), (1, 17, 19, 32, 32), (1, 1, 1, 3, 3),
                                        (1, 60, 256, 5, 129), (1, 60, 257, 5, 9), (1, 60, 200, 5, 130),
-                                       (1, 90, 1100, 21, 75), (2, 70, 230, 9, 131), (1, 40, 1031, 3, 257)])
+                                       (1, 90, 1100, 21, 75), (2, 70, 230, 9, 131), (1, 40, 1031, 3, 257),
+                                       (2, 5, 70, 3, 3), (1, 13, 1030, 9, 5)])
 def test_small_shapes(bz, B, H, W, h, w):
     I = np.stack([gen_document(H, W, 70 + b, noise=10, stain=True, dtype=np.float32) for b in range(B)])
     k = np.random.default_rng(B * H).uniform(0.2, 0.5, size=B).astype(np.float32)
