@@ -190,9 +190,12 @@ typedef struct {
 } bz_global;
 
 /*
- * Compute the global statistics of I into `stats` (device).  Three small
- * kernels on `stream` (reset, accumulate, finish); no memset, so the call can
- * be captured in a graph.  Deterministic (integer atomics).
+ * Compute the global statistics of I into `stats` (device).  Two small
+ * kernels on `stream`: a reset, then an accumulation whose last workgroup
+ * forms mean and std (meanwhile the record's n counts the finished
+ * workgroups, so the record is complete only when the call's work is).  No
+ * memset, so the call can be captured in a graph.  Deterministic (integer
+ * atomics).
  */
 bz_status bz_global_stats(const uint8_t *I, int H, int W, ptrdiff_t ld_I, bz_global *stats,
                           bz_stream stream);

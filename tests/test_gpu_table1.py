@@ -139,3 +139,33 @@ def test_guarded_float32_path_equals_binary64_everywhere(bz, monkeypatch, name):
     ref = bz.table1_threshold(I, 45, 45, name, p, stats=rec)
     torch.cuda.synchronize()
     assert torch.equal(fast[0], ref[0])
+
+
+def test_global_stats_graph_replays(bz):
+    # during the call the record's count tallies the finished workgroups and
+    # the last one forms mean and std; every replay of a captured call leaves
+    # the complete record again, with other work in between
+    H, W = 700, 900
+    host = gen_document(H, W, 21, noise=10.0, stain=True)
+    I = dev(host)
+    r = oracle.global_stats(host)
+    rec = torch.empty(bz.GLOBAL_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+    def call():
+        st = torch.cuda.current_stream().cuda_stream
+        assert bz.lib.bz_global_stats(I.data_ptr(), H, W, W, rec.data_ptr(), st) == 0
+
+    call()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for _ in range(3):
+        rec.fill_(0xAB)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = bz.read_global_stats(rec)
+        assert (got["n"], got["sum"], got["sumsq"], got["min"], got["max"]) == (r["N"], r["T1"], r["T2"], r["L"],
+                                                                                r["max"])
+        assert got["mean"] == r["M"] and got["std"] == r["S"]
