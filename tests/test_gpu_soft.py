@@ -220,3 +220,18 @@ def test_strided_rows_match_contiguous(bz):
         assert np.array_equal(x, z)
     # the padding columns of the outputs are not written
     assert np.all(b[4] == -7.0) and np.all(b[5] == -7.0)
+
+
+@pytest.mark.parametrize("fwd,bwd,adj", [(8, 8, 8), (17, 32, 8), (32, 8, 32), (11, 20, 13)])
+def test_strip_overrides(bz, monkeypatch, fwd, bwd, adj):
+    # the strips of each phase (tuning overrides, 8 to 32 rows) change only
+    # the rounding of the binary64 running sums: every setting stays within
+    # the tolerances of the oracle
+    monkeypatch.setenv("BZ_SOFT_STRIP", str(fwd))
+    monkeypatch.setenv("BZ_SOFT_STRIP_BWD", str(bwd))
+    monkeypatch.setenv("BZ_SOFT_STRIP_ADJ", str(adj))
+    B, H, W, h, w = 2, 100, 300, 21, 15
+    I = np.stack([gen_document(H, W, 90 + b, noise=10, stain=True, dtype=np.float32) for b in range(B)])
+    k = np.random.default_rng(7).uniform(0.2, 0.5, size=B).astype(np.float32)
+    g = np.random.default_rng(8).standard_normal((B, H, W))
+    compare(bz, I, k, 128.0, h, w, g)
