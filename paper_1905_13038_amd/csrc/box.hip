@@ -246,14 +246,17 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
 // Float32 form of a Table 1 rule and its guard.  With m and s within 2 and 3
 // units of 2^-24 (u) of their values, first-order error bounds of the float32
 // threshold against the binary64 one, relative to the magnitude mag of its
-// terms, are about: Wolf 12u, NICK 7u, Rais 25u, Phansalkar (13 + 4|q m|)u
-// of |m| C with C = 1 + |p| e^(-qm) + |k|(1 + s/R), and Feng
+// terms, are about: Wolf 12u, NICK 7.5u (the native square root, within
+// 1 ulp), Rais 26u (the quotient as a product with the native reciprocal,
+// within 1 ulp), Phansalkar (14 + 5|q m|)u of |m| C with
+// C = 1 + |p| e^(-qm) + |k|(1 + s/R) (e^(-qm) as the native 2^(-qm log2 e):
+// within 1.42u, plus |q m| u from the rounded argument), and Feng
 // (11 + |g|(6.1 + 2.1 |log2 x|))u with x = s/R.  For Feng, x^g is
 // 2^(g log2 x) from the native log2 and exp2, which, checked over every
 // float32 input in the ranges used, are within 2u max(1, |log2 x|)
 // (absolute) and 1.42u (relative); x is within 4u, so x^g is within
 // (1.5 + |g|(6.1 + 2.1 |log2 x|))u.  The guard G mag takes 2^-18 (64u) for
-// Wolf, 2^-19 (32u) for NICK, 2^-18 for Phansalkar (mag scaled by 1 + |q m|),
+// Wolf, 2^-18 for NICK, 2^-18 for Phansalkar (mag scaled by 1 + |q m|),
 // 2^-17 for Rais and 2^-19 for Feng (mag scaled by 2 + |g|(1 + |log2 x|)):
 // a factor of 4.5 or more over the bounds.  Where |I - t32| > G mag the float32 and
 // binary64 decisions agree; other pixels, and any non-finite value, go to
@@ -281,10 +284,9 @@ __device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, dou
     f.L = (float)L;
     f.MS = (float)M * (float)S;
     f.pow0 = tp[3] > 0.0 ? 0.0f : tp[3] == 0.0 ? 1.0f : __builtin_inff();
-    f.G = rule == T1_WOLF                         ? 0x1p-18f
-          : rule == T1_NICK || rule == T1_FENG    ? 0x1p-19f
-          : rule == T1_PHANSALKAR                 ? 0x1p-18f
-                                                  : 0x1p-17f;  // T1_RAIS
+    f.G = rule == T1_WOLF || rule == T1_NICK || rule == T1_PHANSALKAR ? 0x1p-18f
+          : rule == T1_FENG                                           ? 0x1p-19f
+                                                                      : 0x1p-17f;  // T1_RAIS
     return f;
 }
 
@@ -300,18 +302,18 @@ __device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, f
         t = m - b * a;
         mag = fabsf(m) + fabsf(f.p0) * (fabsf(m) + fabsf(f.L)) * (1.0f + s * f.rR);
     } else if (f.rule == T1_NICK) {
-        const float r = sqrtf(fmaf(s, s, m * m * (1.0f - rn)));
+        const float r = __builtin_amdgcn_sqrtf(fmaf(s, s, m * m * (1.0f - rn)));
         t = fmaf(f.p0, r, m);
         mag = fabsf(m) + fabsf(f.p0) * r;
     } else if (f.rule == T1_RAIS) {
         const float a = m * s;
         const float e = fmaxf(a, f.MS);
-        const float q = e > 0.0f ? (a - f.MS) / e : 0.0f;
+        const float q = e > 0.0f ? (a - f.MS) * __builtin_amdgcn_rcpf(e) : 0.0f;
         t = fmaf(0.3f * s, q, m);
         mag = fabsf(m) + 0.3f * s;
     } else if (f.rule == T1_PHANSALKAR) {
         const float qm = f.p1 * m;
-        const float ex = expf(-qm);
+        const float ex = __builtin_amdgcn_exp2f(-qm * 1.44269504088896340736f);  // e^(-qm)
         const float c = 1.0f + f.p0 * ex + f.p2 * (s * f.rR - 1.0f);
         t = m * c;
         mag = fabsf(m) * (1.0f + fabsf(f.p0) * ex + fabsf(f.p2) * (1.0f + s * f.rR)) * (1.0f + fabsf(qm));
