@@ -243,6 +243,11 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
     return (double)I < t;
 }
 
+// Kernels of the Table 1 rules are specialised to the rule: their MODE
+// template argument is MODE_T1_BASE + the rule (the job's mode stays
+// MODE_TABLE1), so each keeps only its rule's constants and arithmetic.
+constexpr int MODE_T1_BASE = 16;
+
 // Float32 form of a Table 1 rule and its guard.  With m and s within 2 and 3
 // units of 2^-24 (u) of their values, first-order error bounds of the float32
 // threshold against the binary64 one, relative to the magnitude mag of its
@@ -292,26 +297,27 @@ __device__ __forceinline__ T1Fast t1_fast_params(int rule, const double *tp, dou
 
 // d = I - t32 and the guard g = G mag: the float32 decision is the sign of d,
 // valid where |d| > g.
+template <int RULE>
 __device__ __forceinline__ void table1_fast(const T1Fast &f, float m, float s, float rn, float I,
                                             float &d, float &g)
 {
     float t, mag;
-    if (f.rule == T1_WOLF) {
+    if constexpr (RULE == T1_WOLF) {
         const float a = 1.0f - s * f.rR;
         const float b = f.p0 * (m - f.L);
         t = m - b * a;
         mag = fabsf(m) + fabsf(f.p0) * (fabsf(m) + fabsf(f.L)) * (1.0f + s * f.rR);
-    } else if (f.rule == T1_NICK) {
+    } else if constexpr (RULE == T1_NICK) {
         const float r = __builtin_amdgcn_sqrtf(fmaf(s, s, m * m * (1.0f - rn)));
         t = fmaf(f.p0, r, m);
         mag = fabsf(m) + fabsf(f.p0) * r;
-    } else if (f.rule == T1_RAIS) {
+    } else if constexpr (RULE == T1_RAIS) {
         const float a = m * s;
         const float e = fmaxf(a, f.MS);
         const float q = e > 0.0f ? (a - f.MS) * __builtin_amdgcn_rcpf(e) : 0.0f;
         t = fmaf(0.3f * s, q, m);
         mag = fabsf(m) + 0.3f * s;
-    } else if (f.rule == T1_PHANSALKAR) {
+    } else if constexpr (RULE == T1_PHANSALKAR) {
         const float qm = f.p1 * m;
         const float ex = __builtin_amdgcn_exp2f(-qm * 1.44269504088896340736f);  // e^(-qm)
         const float c = 1.0f + f.p0 * ex + f.p2 * (s * f.rR - 1.0f);
@@ -377,7 +383,8 @@ template <int MODE, bool AL, bool MS>
 __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32_t *smem)
 {
     constexpr int R = ROWS_PER_GROUP;
-    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK || MODE == MODE_TABLE1);
+    constexpr bool T1 = MODE >= MODE_T1_BASE;  // a Table 1 rule, MODE - MODE_T1_BASE
+    constexpr bool need_i = (MODE == MODE_SAUVOLA || MODE == MODE_NIBLACK || T1);
     const int NT = blockDim.x;
     const int PS = prefix_row_words(NT);
     const int BW = box_buffer_words(NT);
@@ -488,7 +495,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
                          : -GUARD;
     // Table 1 rules: the image's global minimum, mean and standard deviation
     double gL = 0.0, gM = 0.0, gS = 0.0;
-    if (MODE == MODE_TABLE1 && a.gs != nullptr) {
+    if (T1 && a.gs != nullptr) {
         gL = (double)a.gs->min;
         gM = a.gs->mean;
         gS = a.gs->stdev;
@@ -717,11 +724,12 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
             }
             if (MODE == MODE_MEANSTD) continue;
             const uint32_t gw = gray_row(gs, r)[tid];  // byte k: column ec0 + 64 k (this lane's word)
-            if (MODE == MODE_TABLE1) {
+            if constexpr (T1) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     float d, g;
-                    table1_fast(t1f, c[k].m, c[k].s, c[k].rn, (float)byte_of(gw, k), d, g);
+                    table1_fast<T1 ? MODE - MODE_T1_BASE : T1_FENG>(t1f, c[k].m, c[k].s, c[k].rn,
+                                                                     (float)byte_of(gw, k), d, g);
                     bits[r][k] = d < 0.0f ? 1u : 0u;
                     if (a.force_ref || !(fabsf(d) > g)) t1near |= 1u << (4 * r + k);
                 }
@@ -738,7 +746,7 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
         if (!need_i) return;
         // pixels within the guard: re-decided with the binary64 sequence
         // (rare; statistics recomputed from LDS, one call site)
-        if (MODE == MODE_TABLE1) {
+        if constexpr (T1) {
             // pixels inside the guard: the binary64 sequence (statistics
             // recomputed from LDS)
             while (t1near != 0) {
@@ -1029,7 +1037,20 @@ hipError_t launch_box(const BoxJob &a, hipStream_t stream)
     case MODE_MEANSTD: return launch_mode<MODE_MEANSTD, true>(a, stream);
     case MODE_SAUVOLA: return ms ? launch_mode<MODE_SAUVOLA, true>(a, stream) : launch_mode<MODE_SAUVOLA, false>(a, stream);
     case MODE_NIBLACK: return ms ? launch_mode<MODE_NIBLACK, true>(a, stream) : launch_mode<MODE_NIBLACK, false>(a, stream);
-    case MODE_TABLE1: return ms ? launch_mode<MODE_TABLE1, true>(a, stream) : launch_mode<MODE_TABLE1, false>(a, stream);
+    case MODE_TABLE1:
+        switch (a.rule) {
+#define BZ_T1_CASE(RULE)                                                                              \
+    case RULE:                                                                                        \
+        return ms ? launch_mode<MODE_T1_BASE + RULE, true>(a, stream)                                 \
+                  : launch_mode<MODE_T1_BASE + RULE, false>(a, stream);
+            BZ_T1_CASE(T1_WOLF)
+            BZ_T1_CASE(T1_FENG)
+            BZ_T1_CASE(T1_RAIS)
+            BZ_T1_CASE(T1_NICK)
+            BZ_T1_CASE(T1_PHANSALKAR)
+#undef BZ_T1_CASE
+        default: return hipErrorInvalidValue;
+        }
     default: return hipErrorInvalidValue;
     }
 }
