@@ -177,14 +177,16 @@ __device__ __attribute__((noinline)) bool below_reference(uint32_t I, uint32_t S
 
 // The other rules of Table 1, decided in binary64 for every pixel: m, s as
 // in below_reference, then the rule's threshold, each operation rounded once
-// (p: the rule's parameters; L, M, S: the image's minimum, mean and standard
-// deviation).  Wolf t = m - k (m - L)(1 - s/R); Feng t = a1 m
+// (RULE: the rule, a template argument so that each kernel carries only its
+// own sequence; p: the rule's parameters; L, M, S: the image's minimum, mean
+// and standard deviation).  Wolf t = m - k (m - L)(1 - s/R); Feng t = a1 m
 // + k1 (s/R)^(1+g) (m - L) + k2 (s/R)^g L; Rais t = m + 0.3 (m s - M S) /
 // max{m s, M S} s (the fraction is 0 where both products are 0); Khurshid
 // (NICK) t = m + k sqrt(s^2 + m^2 (n-1)/n) with the clipped count n for h w;
 // Phansalkar t = m (1 + p e^(-q m) + k (s/R - 1)).
+template <int RULE>
 __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, uint32_t S2,
-                                                       int64_t n, int rule, double p0, double p1,
+                                                       int64_t n, double p0, double p1,
                                                        double p2, double p3, double p4, double L,
                                                        double M, double S)
 {
@@ -195,14 +197,14 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
     const double v = (double)Vn / (nd * nd);
     const double s = __builtin_sqrt(v);
     double t;
-    if (rule == T1_WOLF) {
+    if (RULE == T1_WOLF) {
         double a = s / p1;
         a = 1.0 - a;
         double b = m - L;
         b = p0 * b;
         b = b * a;
         t = m - b;
-    } else if (rule == T1_FENG) {
+    } else if (RULE == T1_FENG) {
         const double x = s / p4;
         const double x1 = pow(x, 1.0 + p3);
         const double x0 = pow(x, p3);
@@ -213,7 +215,7 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
         c = c * L;
         t = a + b;
         t = t + c;
-    } else if (rule == T1_RAIS) {
+    } else if (RULE == T1_RAIS) {
         const double a = m * s, b = M * S;
         const double e = a > b ? a : b;
         double f = 0.0;
@@ -221,7 +223,7 @@ __device__ __attribute__((noinline)) bool table1_below(uint32_t I, uint32_t S1, 
         double g = 0.3 * f;
         g = g * s;
         t = m + g;
-    } else if (rule == T1_NICK) {
+    } else if (RULE == T1_NICK) {
         const double a = s * s;
         double b = m * m;
         const double c = (nd - 1.0) / nd;
@@ -755,10 +757,11 @@ __device__ __forceinline__ void box_tile(const BoxJob &a, int tx, int sy, uint32
                 const int r = i >> 2, k = i & 3;
                 const ColStats c = col_stats(b, r, k, yg + r, false);
                 const uint32_t gv = ((const uint8_t *)gray_row(gs, r))[4 * tid + k];
-                const uint32_t bit = table1_below(gv, c.S1, c.S2, (int64_t)c.n, a.rule, a.tp[0], a.tp[1],
-                                                  a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
-                                         ? 1u
-                                         : 0u;
+                const uint32_t bit =
+                    table1_below<T1 ? MODE - MODE_T1_BASE : T1_FENG>(gv, c.S1, c.S2, (int64_t)c.n, a.tp[0], a.tp[1],
+                                                                     a.tp[2], a.tp[3], a.tp[4], gL, gM, gS)
+                        ? 1u
+                        : 0u;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
 #pragma unroll
