@@ -55,6 +55,9 @@ constexpr size_t HAAR_ROW_LDS = HAAR_ROW_ELEMS * sizeof(uint32_t);
 // output rows per group of k_haar_fused: the next group's row loads are in
 // flight while a group is processed
 constexpr int HAAR_GROUP = 4;
+// priming rows of k_haar_fused loaded together (cells of 16 rows or more;
+// measured on line_v at a = 48: 25 us against 29.8 us four rows at a time)
+constexpr int HAAR_PRIME = 16;
 
 // Workgroup (bx, sy): columns bx*256 .. +255, rows of V y0 = sy*S .. y0+S-1.
 __global__ __launch_bounds__(HAAR_THREADS) void k_haar_v(const uint8_t *__restrict__ I, int64_t ld, int W, int a,
@@ -288,8 +291,27 @@ __global__ __launch_bounds__(64) void k_haar_fused(const uint8_t *__restrict__ I
         uint32_t ev[NDW], od[NDW];
 #pragma unroll
         for (int q = 0; q < NDW; ++q) ev[q] = od[q] = 0u;
+        // the rows in chunks of HAAR_PRIME (all loads of a chunk in flight
+        // together), then the rest four at a time
+        int r = 0;
+        for (; r + HAAR_PRIME <= a; r += HAAR_PRIME) {
+            uint32_t v[HAAR_PRIME][NDW];
+#pragma unroll
+            for (int k = 0; k < HAAR_PRIME; ++k) {
+                const __amdgpu_buffer_rsrc_t d = row_rsrc(r0 + r + k);
+#pragma unroll
+                for (int q = 0; q < NDW; ++q) v[k][q] = load(d, q);
+            }
+#pragma unroll
+            for (int k = 0; k < HAAR_PRIME; ++k)
+#pragma unroll
+                for (int q = 0; q < NDW; ++q) {
+                    ev[q] += v[k][q] & 0x00ff00ffu;
+                    od[q] += __builtin_amdgcn_perm(0u, v[k][q], 0x0c030c01u);  // bytes 1, 3 into 0, 2
+                }
+        }
 #pragma unroll 4
-        for (int r = 0; r < a; ++r) {
+        for (; r < a; ++r) {
             const __amdgpu_buffer_rsrc_t d = row_rsrc(r0 + r);
 #pragma unroll
             for (int q = 0; q < NDW; ++q) {
