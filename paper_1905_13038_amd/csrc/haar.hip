@@ -53,8 +53,11 @@ constexpr int HAAR_STRIP = HAAR_ROWS;
 constexpr int HAAR_ROW_ELEMS = 12288;
 constexpr size_t HAAR_ROW_LDS = HAAR_ROW_ELEMS * sizeof(uint32_t);
 // output rows per group of k_haar_fused: the next group's row loads are in
-// flight while a group is processed
-constexpr int HAAR_GROUP = 4;
+// flight while a group is processed.  Measured on the 4096 x 3072 page
+// (edge_h and checker at 12, line_v and line_h at 48): one row per group
+// 14.8, 16.9, 23.6 and 19.3 us; two 14.7, 17.1, 24.0, 19.9; four 15.4, 18.3,
+// 24.9, 20.3; eight slower still (line_v 31.2).
+constexpr int HAAR_GROUP = 1;
 // priming rows of k_haar_fused loaded together (cells of 16 rows or more;
 // measured on line_v at a = 48: 25 us against 29.8 us four rows at a time)
 constexpr int HAAR_PRIME = 16;
