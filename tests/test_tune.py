@@ -62,3 +62,60 @@ def test_cache_round_trip_keeps_other_entries(tmp_path):
         f.write("{garbage")
     tune.save_table(p, DEV, "batch", {15: 16})
     assert tune.load_table(p, DEV, "batch") == {15: 16}
+
+
+class _FakePlan:
+    """Stands in for a BatchPlan: records the strips it is re-planned with."""
+
+    def __init__(self):
+        self.strips = None
+        self.history = []
+
+    def replan(self, strips):
+        self.strips = list(strips)
+        self.history.append(list(strips))
+
+    def run(self):
+        pass
+
+
+def test_autotune_plan_takes_each_class_best_strip(monkeypatch):
+    # a launch time that is lowest, per window class, at one candidate strip:
+    # the greedy search keeps that strip for every class present and leaves
+    # the plan re-planned with the result
+    params = [{"h": 11}, {"h": 13}, {"h": 51}, {"h": 201}]
+    best = {15: 24, 63: 96, 257: 128}
+    plan = _FakePlan()
+
+    def fake_time(fn, reps):
+        fn()
+        cost = 1000.0
+        for p, s in zip(params, plan.strips):
+            cost += abs(s - best[tune.window_class(p["h"])])
+        return cost
+
+    monkeypatch.setattr(tune, "_time", fake_time)
+    table = tune.autotune_plan(plan, params)
+    # class 257's best is its built-in strip (2 h capped at 128), so it stays out
+    assert table == {15: 24, 63: 96}
+    assert plan.strips == tune.strips_for(params, table) == [24, 24, 96, 128]
+
+
+def test_autotune_plan_keeps_builtin_strips_without_gain(monkeypatch):
+    # gains under min_gain are not taken: the table stays empty and the plan
+    # keeps the built-in strips
+    params = [{"h": 31}, {"h": 75}]
+    plan = _FakePlan()
+    calls = []
+
+    def flat_time(fn, reps):
+        fn()
+        calls.append(list(plan.strips))
+        return 1000.0 - (0.001 if plan.strips[0] == 48 else 0.0)
+
+    monkeypatch.setattr(tune, "_time", flat_time)
+    table = tune.autotune_plan(plan, params, min_gain=0.005)
+    assert table == {}
+    assert plan.strips == [tune.default_strip(31), tune.default_strip(75)]
+    # one baseline, then one trial per candidate and class
+    assert len(calls) == 1 + len(tune.CANDIDATES) * 2
