@@ -310,6 +310,31 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
     // word holding its last byte
     const __amdgpu_buffer_rsrc_t dimg = rsrc(I, vin ? (uint32_t)((int64_t)(H - 1) * ldI + ((W + 3) & ~3)) : 0u);
 
+    // The gray levels of the quads this thread decides in phase 4 (thread i
+    // covers the four columns 4 (i mod 16) .. +3 of tile row i / 16 + 16 k),
+    // loaded now so that their latency hides behind phases 1 to 3: one
+    // aligned dword per quad where vin (past W: unused), else four bytes at
+    // clamped positions; byte j is column x0 + xq + j
+    constexpr int QPR = EXT_T / 4;                // quads per tile row
+    constexpr int PER = EXT_T * QPR / EXT_FT;     // quads per thread
+    const int xq = 4 * (tid % QPR), tr = tid / QPR;
+    uint32_t ivw[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = tr + (EXT_FT / QPR) * k;
+        const int yc = min(y0 + t, H - 1);
+        if (!mask) {
+            ivw[k] = 0u;
+        } else if (vin) {
+            ivw[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(dimg, (int)((int64_t)yc * ldI + x0 + xq), 0, 0);
+        } else {
+            const uint8_t *irow = I + (int64_t)yc * ldI;
+            ivw[k] = 0u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ivw[k] |= (uint32_t)irow[min(x0 + xq + j, W - 1)] << (8 * j);
+        }
+    }
+
     // 1. input tile.  vin: aligned dwords, one per thread and pass (the
     // columns from tx0 rounded down to a multiple of 4), each byte kept where
     // it lies in the tile and the image; otherwise thread (c, r0) takes
@@ -396,28 +421,7 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
     // 4. outputs: thread i covers the four columns 4 (i mod 16) .. +3 of tile
     // row i / 16 + 16 k; as dwords where every row stride and base is a
     // multiple of 4 (vec) and the four columns lie in the image, else as
-    // bytes
-    constexpr int QPR = EXT_T / 4;                // quads per tile row
-    constexpr int PER = EXT_T * QPR / EXT_FT;     // quads per thread
-    const int xq = 4 * (tid % QPR), tr = tid / QPR;
-    uint32_t iv[PER][4];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int t = tr + (EXT_FT / QPR) * k;
-        const int yc = min(y0 + t, H - 1);
-        if (vin) {
-            // the aligned dword of columns x0 + xq .. +3 (past W: unused)
-            const uint32_t q4 = mask ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
-                                           dimg, (int)((int64_t)yc * ldI + x0 + xq), 0, 0)
-                                     : 0u;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) iv[k][j] = (q4 >> (8 * j)) & 0xffu;
-        } else {
-            const uint8_t *irow = I + (int64_t)yc * ldI;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) iv[k][j] = mask ? irow[min(x0 + xq + j, W - 1)] : 0u;
-        }
-    }
+    // bytes (their gray levels were loaded before phase 1)
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = tr + (EXT_FT / QPR) * k;
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(EXT_FT) void k_ext_fused(const uint8_t *__restrict_
             const uint32_t e = ext_fold(ext_max2(ext_spread(tsu[t * CP + xq + j]), ext_spread(tpr[t * CP + xq + j])));
             hi[j] = e & 0xffu;
             lo[j] = 255u - (e >> 8);
-            mk[j] = ((int)(hi[j] - lo[j]) >= cmin && 2 * iv[k][j] < lo[j] + hi[j]) ? 1u : 0u;
+            mk[j] = ((int)(hi[j] - lo[j]) >= cmin && 2 * ((ivw[k] >> (8 * j)) & 0xffu) < lo[j] + hi[j]) ? 1u : 0u;
         }
         uint8_t *pmx = mx + (int64_t)yy * ldE + xx, *pmn = mn + (int64_t)yy * ldE + xx;
         uint8_t *pmk = mask ? mask + (int64_t)yy * ldM + xx : nullptr;
