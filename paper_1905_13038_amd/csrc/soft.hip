@@ -377,6 +377,11 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
         }
         __syncthreads();
 
+        // the row's epilogue at raised wave priority: waves storing a row's
+        // outputs issue ahead of waves still in the column pass (measured on
+        // 32 pages of 1024 x 1024: backward 425 -> 418 us at h = 75, 361 ->
+        // 358 us at h = 32; the forward unchanged)
+        __builtin_amdgcn_s_setprio(3);
         float rowk = 0.0f, rowR = 0.0f;  // this row's dL/dk and dL/dR / (-k / R^2) terms
         const int nr = min(y + a.u, H - 1) - max(y - a.o, -1);
         const double rnr = recip64(nr);
@@ -459,6 +464,7 @@ __global__ __launch_bounds__(NT) void k_soft(SoftArgs a)
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(g2), f2, (int)oe[j], (int)soF, 0);
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(delta * rtau), f3, (int)oe[j], (int)soF, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (PH == BWD1) {
             dk_acc += (double)rowk;
             dR_acc += (double)rowR * cR64;
