@@ -108,3 +108,15 @@ def test_haar_rows_wider_than_the_row_kernel(bz, monkeypatch, kind, H, W, a, b):
     # of the two-launch form
     monkeypatch.setenv("BZ_HAAR_FUSED", "0")
     check(bz, gen_document(H, W, 600 + kind.__len__(), noise=10.0, stain=True), a, b, kind)
+
+
+@pytest.mark.parametrize("kind", sorted(KINDS))
+@pytest.mark.parametrize("H,W,a,b", [(300, 400, 17, 5), (200, 256, 33, 3), (260, 132, 16, 9), (64, 64, 20, 20)])
+def test_haar_fused_priming_chunks_and_tail(bz, kind, H, W, a, b):
+    # cells of 16 rows or more prime in chunks of 16 rows, then the rest four
+    # at a time: cell heights with and without a remainder, on aligned rows
+    # (the single-launch form)
+    kv, kh = bz.HAAR[kind][1]
+    if kv * a > H or kh * b > W:
+        pytest.skip("template larger than the image")
+    check(bz, gen_document(H, W, 700 + a, noise=10.0, stain=True), a, b, kind)

@@ -169,3 +169,16 @@ def test_global_stats_graph_replays(bz):
         assert (got["n"], got["sum"], got["sumsq"], got["min"], got["max"]) == (r["N"], r["T1"], r["T2"], r["L"],
                                                                                 r["max"])
         assert got["mean"] == r["M"] and got["std"] == r["S"]
+
+
+@pytest.mark.parametrize("blocks", ["1", "3", "128", "1000"])
+def test_global_stats_any_grid(bz, monkeypatch, blocks):
+    # the last of the accumulating workgroups forms mean and std, whatever
+    # their number (BZ_GSTATS_BLOCKS, capped at the row count)
+    monkeypatch.setenv("BZ_GSTATS_BLOCKS", blocks)
+    for H, W in ((257, 300), (5, 4100)):
+        I = gen_document(H, W, 90 + H, noise=10.0, stain=True)
+        g = bz.read_global_stats(bz.global_stats(dev(I)))
+        r = oracle.global_stats(I)
+        assert (g["n"], g["sum"], g["sumsq"], g["min"], g["max"]) == (r["N"], r["T1"], r["T2"], r["L"], r["max"])
+        assert g["mean"] == r["M"] and g["std"] == r["S"]
